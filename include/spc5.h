@@ -1,0 +1,193 @@
+/*
+ * spc5.h -- C ABI of the MI355X (gfx950) SPC5 sparse matrix/vector library.
+ *
+ * Method: Regnault & Bramas, "SPC5: an efficient SpMV framework vectorized
+ * using ARM SVE and x86 AVX-512", arXiv 2307.14774.
+ *
+ * The problem statement is the one of Algorithm 1 (input: x and a matrix in
+ * the beta(r,c) block format; output: y = A x), with the matrix handed over
+ * in CSR (Section 2.3) and converted to SPC5 beta(r,c) (Section 2.4).
+ *
+ * beta(r,c) storage, as held on the device by a spc5_matrix:
+ *   rows are grouped in panels of r consecutive rows, npanels = ceil(nrows/r);
+ *   blk_ptr[npanels+1]  int32  block range of each panel        (block_rowptr)
+ *   blk_col[nblocks]    int32  anchor column of each block      (block_colidx)
+ *   masks[nblocks*r]    uint8 for c <= 8, uint16 for c > 8;
+ *                              mask of row i of block b at b*r+i (block_masks)
+ *   values[nnz]         packed nonzeros, block by block, row 0..r-1 inside a
+ *                       block, ascending column inside a row   (values)
+ * Bit k (least significant = 0) of a row mask marks column anchor+k
+ * (Fig. 3 caption).  A block is anchored at the smallest column not yet
+ * covered among its panel's rows and spans [anchor, anchor+c) (Section 2.4).
+ * This layout is exported bit for bit by spc5_export().
+ *
+ * Conventions for every call:
+ *  - Integer-returning calls return SPC5_OK (0) or a negative spc5_status;
+ *    spc5_last_error() then holds a message for the calling thread.
+ *  - No call throws; no call keeps a pointer to caller memory after it
+ *    returns.
+ *  - "device" pointers are HIP device allocations (e.g. torch tensors'
+ *    data_ptr()) of the matrix's value type: double for SPC5_F64, float for
+ *    SPC5_F32.  "host" pointers are ordinary CPU memory.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Compute calls are asynchronous on that stream; argument checks are
+ *    synchronous.
+ *  - A matrix handle is immutable after creation except for its schedule
+ *    (spc5_set_schedule); concurrent compute calls on one handle from several
+ *    streams are allowed.  The caller must not free a handle while work that
+ *    uses it is pending.
+ *  - Calls must be made with the HIP device that was current at creation.
+ */
+#ifndef SPC5_H
+#define SPC5_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spc5_matrix spc5_matrix;   /* opaque SPC5 beta(r,c) matrix */
+typedef struct spc5_csr spc5_csr;         /* opaque CSR matrix (comparison kernel) */
+typedef struct spc5_batch spc5_batch;     /* opaque batch of SPC5 matrices */
+
+typedef enum { SPC5_F64 = 0, SPC5_F32 = 1 } spc5_dtype;
+
+typedef enum {
+    SPC5_OK = 0,
+    SPC5_EINVAL = -1,       /* NULL pointer, negative size, bad enum value     */
+    SPC5_EBADCSR = -2,      /* malformed CSR (see csr_to_spc5)                 */
+    SPC5_ENOMEM = -3,       /* device or host allocation failed                */
+    SPC5_EDEVICE = -4,      /* HIP runtime or launch error                     */
+    SPC5_EUNSUPPORTED = -5  /* shape or size outside what the library handles  */
+} spc5_status;
+
+typedef struct {
+    int64_t nrows, ncols, nnz;
+    int64_t nblocks, npanels;
+    int32_t r, c;
+    int32_t dtype;            /* spc5_dtype */
+    int32_t mask_bytes;       /* 1 (c <= 8) or 2 (c > 8) */
+    int32_t panels_per_tile;  /* current schedule: panels handled by one wavefront */
+    int32_t reserved;
+    int64_t ntiles;           /* wavefront tiles of one forward launch */
+    double fill;              /* nnz / (nblocks * r * c), Table 1's block filling */
+    int64_t spmv_bytes;       /* algorithmic bytes moved by one y = A x:
+                                 values + anchors + masks + blk_ptr + x + y */
+    int64_t device_bytes;     /* device memory held by the handle */
+} spc5_info;
+
+/* ---------------------------------------------------------------- creation */
+
+/* Convert a CSR matrix to SPC5 beta(r,c) on the device (Section 2.4).
+ *  nrows, ncols >= 0, ncols <= 2^31-1;
+ *  rowptr  host int64[nrows+1], rowptr[0] == 0, non-decreasing;
+ *  colidx  host int32[nnz], nnz = rowptr[nrows], strictly increasing inside
+ *          each row and in [0, ncols);
+ *  values  host, nnz entries of double (SPC5_F64) or float (SPC5_F32);
+ *          explicit zeros and non-finite values are kept as entries;
+ *  1 <= r <= 8, 1 <= c <= 16.
+ * The inputs are copied; the caller keeps them.  On success *out owns device
+ * memory released by spc5_free; on failure *out is NULL.
+ * Errors: SPC5_EINVAL (NULL out/array, negative size, bad dtype),
+ * SPC5_EBADCSR (rowptr[0] != 0, decreasing rowptr, column out of range,
+ * unsorted or duplicate column in a row), SPC5_EUNSUPPORTED (r or c out of
+ * range, nnz or nblocks >= 2^31, ncols >= 2^31), SPC5_ENOMEM, SPC5_EDEVICE.
+ * Synchronous: returns after the device arrays are complete. */
+int csr_to_spc5(int64_t nrows, int64_t ncols, const int64_t *rowptr,
+                const int32_t *colidx, const void *values, spc5_dtype dtype,
+                int r, int c, spc5_matrix **out);
+
+/* Release a matrix (NULL is ignored). */
+void spc5_free(spc5_matrix *A);
+
+/* Shape, sizes and schedule of a matrix.  out: host. */
+int spc5_get_info(const spc5_matrix *A, spc5_info *out);
+
+/* Copy the beta(r,c) arrays back to host memory, in the layout described at
+ * the top of this file (blk_ptr widened to int64 for the caller).  Any output
+ * pointer may be NULL to skip it.  Sizes: blk_ptr int64[npanels+1],
+ * blk_col int32[nblocks], masks uint8/uint16[nblocks*r] (mask_bytes each),
+ * values[nnz] of the matrix dtype.  Synchronous. */
+int spc5_export(const spc5_matrix *A, int64_t *blk_ptr, int32_t *blk_col,
+                void *masks, void *values);
+
+/* Schedule: number of consecutive panels one wavefront handles
+ * (1..64; 0 restores the default chosen from the mean block rows per panel).
+ * Not safe to call while compute calls on A are in flight. */
+int spc5_set_schedule(spc5_matrix *A, int panels_per_tile);
+
+/* ---------------------------------------------------------------- compute */
+
+/* y[0..nrows) = A x[0..ncols) (Algorithm 1, with y overwritten: rows without
+ * entries get 0).  x, y: device, matrix dtype, must not overlap.
+ * Errors: SPC5_EINVAL (NULL A, or NULL x/y while the matrix is non-empty),
+ * SPC5_EDEVICE. */
+int spc5_spmv(const spc5_matrix *A, const void *x, void *y, void *stream);
+
+/* Same product with the packed values taken from `values` (device,
+ * nnz entries, the packed order of spc5_export) instead of the matrix's own:
+ * y = A(theta) x, used by the differentiable path. */
+int spc5_spmv_values(const spc5_matrix *A, const void *values, const void *x,
+                     void *y, void *stream);
+
+/* xbar[0..ncols) = A^T ybar[0..nrows): the transposed product, scattered from
+ * the SPC5 blocks (each set mask bit adds value * ybar[row] to
+ * xbar[anchor+k]).  xbar is overwritten (zeroed on the stream first).
+ * values: device packed values, or NULL for the matrix's own.  The
+ * accumulation order varies between runs (atomic adds).  Device pointers. */
+int spc5_spmv_transpose(const spc5_matrix *A, const void *ybar, void *xbar,
+                        void *stream);
+int spc5_spmv_transpose_values(const spc5_matrix *A, const void *values,
+                               const void *ybar, void *xbar, void *stream);
+
+/* Gradient of <ybar, A(theta) x> with respect to the packed values theta:
+ * vbar[v] = ybar[row(v)] * x[col(v)], in packed order (nnz entries).
+ * Device pointers. */
+int spc5_values_grad(const spc5_matrix *A, const void *ybar, const void *x,
+                     void *vbar, void *stream);
+
+/* Y = A X for nrhs right-hand sides: X device [ncols][nrhs] row-major,
+ * Y device [nrows][nrhs] row-major (overwritten).  1 <= nrhs <= 64. */
+int spc5_spmm(const spc5_matrix *A, int nrhs, const void *X, void *Y, void *stream);
+
+/* ---------------------------------------------------------------- batches */
+
+/* Group matrices of one dtype so that Y_m = A_m X_m for all m runs as one
+ * launch (tiles of every matrix in a single grid).  The batch keeps pointers
+ * to the handles (which must outlive it) and owns its own device tables.
+ * Synchronous. */
+int spc5_batch_create(int nmat, spc5_matrix *const *mats, spc5_batch **out);
+void spc5_batch_free(spc5_batch *B);
+
+/* X[m], Y[m]: host arrays of nmat device pointers, laid out as in spc5_spmm
+ * with the same nrhs for every matrix. */
+int spc5_batch_spmm(spc5_batch *B, int nrhs, const void *const *X,
+                    void *const *Y, void *stream);
+
+/* ---------------------------------------------------------------- CSR */
+
+/* Plain CSR matrix on the device, the comparison kernel (Section 2.3's CSR;
+ * the paper's scalar CSR baseline).  Same argument rules as csr_to_spc5. */
+int spc5_csr_create(int64_t nrows, int64_t ncols, const int64_t *rowptr,
+                    const int32_t *colidx, const void *values, spc5_dtype dtype,
+                    spc5_csr **out);
+void spc5_csr_free(spc5_csr *A);
+/* y = A x with the plain CSR storage; device pointers. */
+int spc5_csr_spmv(const spc5_csr *A, const void *x, void *y, void *stream);
+/* Algorithmic bytes of one CSR product (values + colidx + rowptr + x + y). */
+int64_t spc5_csr_bytes(const spc5_csr *A);
+
+/* ---------------------------------------------------------------- misc */
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *spc5_last_error(void);
+
+/* Library version string. */
+const char *spc5_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPC5_H */

@@ -1,0 +1,383 @@
+// C ABI of libspc5: argument checks, CSR validation, device memory ownership
+// and kernel dispatch.  See include/spc5.h for the contract of every call.
+#include "spc5_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <utility>
+#include <vector>
+
+namespace spc5 {
+
+static thread_local std::string g_err;
+
+int fail(int status, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    const int st = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? SPC5_ENOMEM
+                                                                             : SPC5_EDEVICE;
+    return fail(st, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+int default_ppt(double blockrows_per_panel) {
+    // aim at about four sweeps of 64 block rows per wavefront
+    if (!(blockrows_per_panel > 0.0)) return 64;
+    const double p = std::floor(256.0 / blockrows_per_panel + 0.5);
+    return (int)std::max(1.0, std::min(64.0, p));
+}
+
+// Test hook: SPC5_TEST_FAIL_ALLOC=1 makes every device allocation of the
+// creation calls fail, to exercise the SPC5_ENOMEM path.
+static bool alloc_fail_hook() {
+    const char *e = getenv("SPC5_TEST_FAIL_ALLOC");
+    return e && e[0] == '1';
+}
+
+// Host-side CSR validation, parallel over row ranges.
+static int validate_csr(int64_t nrows, int64_t ncols, const int64_t *rowptr,
+                        const int32_t *colidx, const void *values, int64_t *nnz_out) {
+    if (!rowptr) return fail(SPC5_EINVAL, "rowptr is NULL");
+    if (rowptr[0] != 0) return fail(SPC5_EBADCSR, "rowptr[0] = %lld, expected 0",
+                                    (long long)rowptr[0]);
+    for (int64_t i = 0; i < nrows; ++i)
+        if (rowptr[i + 1] < rowptr[i])
+            return fail(SPC5_EBADCSR, "rowptr decreases at row %lld", (long long)i);
+    const int64_t nnz = rowptr[nrows];
+    if (nnz >= ((int64_t)1 << 31))
+        return fail(SPC5_EUNSUPPORTED, "nnz = %lld does not fit int32 device indices",
+                    (long long)nnz);
+    if (nnz > 0 && (!colidx || !values)) return fail(SPC5_EINVAL, "colidx or values is NULL");
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (nnz < (1 << 20)) nth = 1;
+    std::vector<int64_t> bad(nth, -1);
+    std::vector<int> kind(nth, 0);
+    auto work = [&](unsigned t) {
+        const int64_t lo = nrows * t / nth, hi = nrows * (t + 1) / nth;
+        for (int64_t i = lo; i < hi; ++i) {
+            int64_t prev = -1;
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                const int64_t cc = colidx[k];
+                if (cc < 0 || cc >= ncols) { bad[t] = i; kind[t] = 1; return; }
+                if (cc <= prev) { bad[t] = i; kind[t] = 2; return; }
+                prev = cc;
+            }
+        }
+    };
+    if (nth == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nth; ++t) th.emplace_back(work, t);
+        for (auto &t : th) t.join();
+    }
+    for (unsigned t = 0; t < nth; ++t)
+        if (bad[t] >= 0)
+            return fail(SPC5_EBADCSR, kind[t] == 1 ? "column out of range in row %lld"
+                                                   : "unsorted or duplicate column in row %lld",
+                        (long long)bad[t]);
+    *nnz_out = nnz;
+    return SPC5_OK;
+}
+
+static int check_create_args(int64_t nrows, int64_t ncols, spc5_dtype dtype) {
+    if (nrows < 0 || ncols < 0) return fail(SPC5_EINVAL, "negative matrix size");
+    if (dtype != SPC5_F64 && dtype != SPC5_F32) return fail(SPC5_EINVAL, "bad dtype %d", (int)dtype);
+    if (ncols > INT32_MAX) return fail(SPC5_EUNSUPPORTED, "ncols >= 2^31");
+    if (nrows >= ((int64_t)1 << 40)) return fail(SPC5_EUNSUPPORTED, "nrows too large");
+    return SPC5_OK;
+}
+
+// Device allocation wrapper honouring the test hook.
+static hipError_t dmalloc(void **p, size_t bytes) {
+    if (alloc_fail_hook()) return hipErrorOutOfMemory;
+    return hipMalloc(p, bytes < 256 ? 256 : bytes);
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard() {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+static void free_matrix(spc5_matrix *A) {
+    if (!A) return;
+    DeviceGuard g(A->device);
+    if (A->blk_ptr) (void)hipFree(A->blk_ptr);
+    if (A->blk_col) (void)hipFree(A->blk_col);
+    if (A->masks) (void)hipFree(A->masks);
+    if (A->val) (void)hipFree(A->val);
+    if (A->panel_val) (void)hipFree(A->panel_val);
+    delete A;
+}
+
+}  // namespace spc5
+
+using namespace spc5;
+
+extern "C" {
+
+const char *spc5_last_error(void) { return g_err.c_str(); }
+
+const char *spc5_version(void) { return "spc5-mi355x 0.1 (gfx950)"; }
+
+int csr_to_spc5(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *colidx,
+                const void *values, spc5_dtype dtype, int r, int c, spc5_matrix **out) {
+    if (!out) return fail(SPC5_EINVAL, "out is NULL");
+    *out = nullptr;
+    int st;
+    if ((st = check_create_args(nrows, ncols, dtype)) != SPC5_OK) return st;
+    if (r < 1 || r > 8 || c < 1 || c > 16)
+        return fail(SPC5_EUNSUPPORTED, "beta(%d,%d): need 1 <= r <= 8 and 1 <= c <= 16", r, c);
+    int64_t nnz = 0;
+    if ((st = validate_csr(nrows, ncols, rowptr, colidx, values, &nnz)) != SPC5_OK) return st;
+    const int64_t npanels = (nrows + r - 1) / r;
+    if (npanels >= ((int64_t)1 << 31) - 1)
+        return fail(SPC5_EUNSUPPORTED, "too many panels for int32 indices");
+
+    spc5_matrix *A = new (std::nothrow) spc5_matrix();
+    if (!A) return fail(SPC5_ENOMEM, "host allocation failed");
+    A->nrows = nrows; A->ncols = ncols; A->nnz = nnz; A->npanels = npanels;
+    A->r = r; A->c = c; A->dtype = dtype; A->mask_bytes = c <= 8 ? 1 : 2;
+    hipError_t e = hipGetDevice(&A->device);
+    if (e != hipSuccess) { delete A; return hip_fail(e, "hipGetDevice"); }
+    const int vb = dtype == SPC5_F64 ? 8 : 4;
+    int64_t *d_rowptr = nullptr;
+    int32_t *d_colidx = nullptr;
+    void *d_val = nullptr;
+    auto drop = [&]() {
+        if (d_rowptr) (void)hipFree(d_rowptr);
+        if (d_colidx) (void)hipFree(d_colidx);
+        if (d_val) (void)hipFree(d_val);
+    };
+    if ((e = dmalloc((void **)&d_rowptr, (size_t)(nrows + 1) * 8)) != hipSuccess ||
+        (e = dmalloc((void **)&d_colidx, (size_t)nnz * 4)) != hipSuccess ||
+        (e = dmalloc(&d_val, (size_t)nnz * vb)) != hipSuccess) {
+        drop();
+        free_matrix(A);
+        return hip_fail(e, "allocating device CSR");
+    }
+    if ((e = hipMemcpy(d_rowptr, rowptr, (size_t)(nrows + 1) * 8, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (nnz > 0 &&
+         ((e = hipMemcpy(d_colidx, colidx, (size_t)nnz * 4, hipMemcpyHostToDevice)) !=
+              hipSuccess ||
+          (e = hipMemcpy(d_val, values, (size_t)nnz * vb, hipMemcpyHostToDevice)) !=
+              hipSuccess))) {
+        drop();
+        free_matrix(A);
+        return hip_fail(e, "uploading CSR");
+    }
+    st = convert_on_device(A, d_rowptr, d_colidx, d_val);
+    drop();
+    if (st != SPC5_OK) { free_matrix(A); return st; }
+    A->ppt = default_ppt(npanels ? (double)A->nblocks * r / (double)npanels : 0.0);
+    *out = A;
+    return SPC5_OK;
+}
+
+void spc5_free(spc5_matrix *A) { free_matrix(A); }
+
+int spc5_get_info(const spc5_matrix *A, spc5_info *out) {
+    if (!A || !out) return fail(SPC5_EINVAL, "NULL argument");
+    memset(out, 0, sizeof *out);
+    out->nrows = A->nrows; out->ncols = A->ncols; out->nnz = A->nnz;
+    out->nblocks = A->nblocks; out->npanels = A->npanels;
+    out->r = A->r; out->c = A->c; out->dtype = A->dtype; out->mask_bytes = A->mask_bytes;
+    out->panels_per_tile = A->ppt;
+    out->ntiles = (A->npanels + A->ppt - 1) / A->ppt;
+    out->fill = A->nblocks ? (double)A->nnz / ((double)A->nblocks * A->r * A->c) : 0.0;
+    const int64_t vb = A->dtype == SPC5_F64 ? 8 : 4;
+    out->spmv_bytes = vb * A->nnz + 4 * A->nblocks + (int64_t)A->r * A->mask_bytes * A->nblocks +
+                      4 * (A->npanels + 1) + vb * A->ncols + vb * A->nrows;
+    out->device_bytes = vb * A->nnz + 4 * A->nblocks + (int64_t)A->r * A->mask_bytes * A->nblocks +
+                        8 * (A->npanels + 1);
+    return SPC5_OK;
+}
+
+int spc5_export(const spc5_matrix *A, int64_t *blk_ptr, int32_t *blk_col, void *masks,
+                void *values) {
+    if (!A) return fail(SPC5_EINVAL, "A is NULL");
+    DeviceGuard g(A->device);
+    if (!g.ok) return fail(SPC5_EDEVICE, "cannot select the matrix's device");
+    hipError_t e;
+    if (blk_ptr) {
+        std::vector<int32_t> tmp((size_t)A->npanels + 1);
+        if ((e = hipMemcpy(tmp.data(), A->blk_ptr, tmp.size() * 4, hipMemcpyDeviceToHost)) !=
+            hipSuccess)
+            return hip_fail(e, "exporting blk_ptr");
+        for (size_t i = 0; i < tmp.size(); ++i) blk_ptr[i] = tmp[i];
+    }
+    if (blk_col && A->nblocks &&
+        (e = hipMemcpy(blk_col, A->blk_col, (size_t)A->nblocks * 4, hipMemcpyDeviceToHost)) !=
+            hipSuccess)
+        return hip_fail(e, "exporting blk_col");
+    if (masks && A->nblocks &&
+        (e = hipMemcpy(masks, A->masks, (size_t)A->nblocks * A->r * A->mask_bytes,
+                       hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "exporting masks");
+    if (values && A->nnz &&
+        (e = hipMemcpy(values, A->val, (size_t)A->nnz * (A->dtype == SPC5_F64 ? 8 : 4),
+                       hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "exporting values");
+    return SPC5_OK;
+}
+
+int spc5_set_schedule(spc5_matrix *A, int ppt) {
+    if (!A) return fail(SPC5_EINVAL, "A is NULL");
+    if (ppt < 0 || ppt > 64) return fail(SPC5_EINVAL, "panels_per_tile must be in 0..64");
+    A->ppt = ppt ? ppt
+                 : default_ppt(A->npanels ? (double)A->nblocks * A->r / (double)A->npanels : 0.0);
+    return SPC5_OK;
+}
+
+// A vector pointer may be NULL only when its length is zero.
+static int compute_guard(const spc5_matrix *A,
+                         std::initializer_list<std::pair<const void *, int64_t>> vecs) {
+    if (!A) return fail(SPC5_EINVAL, "A is NULL");
+    for (const auto &v : vecs)
+        if (!v.first && v.second > 0) return fail(SPC5_EINVAL, "NULL vector");
+    return SPC5_OK;
+}
+
+int spc5_spmv(const spc5_matrix *A, const void *x, void *y, void *stream) {
+    int st = compute_guard(A, {{x, A ? A->ncols : 0}, {y, A ? A->nrows : 0}});
+    if (st) return st;
+    DeviceGuard g(A->device);
+    hipError_t e = launch_spmv(A, nullptr, x, y, (hipStream_t)stream);
+    return e == hipSuccess ? SPC5_OK : hip_fail(e, "spc5_spmv launch");
+}
+
+int spc5_spmv_values(const spc5_matrix *A, const void *values, const void *x, void *y,
+                     void *stream) {
+    int st = compute_guard(A, {{x, A ? A->ncols : 0}, {y, A ? A->nrows : 0}});
+    if (st) return st;
+    if (!values && A->nnz) return fail(SPC5_EINVAL, "values is NULL");
+    DeviceGuard g(A->device);
+    hipError_t e = launch_spmv(A, values ? values : A->val, x, y, (hipStream_t)stream);
+    return e == hipSuccess ? SPC5_OK : hip_fail(e, "spc5_spmv_values launch");
+}
+
+int spc5_spmv_transpose(const spc5_matrix *A, const void *ybar, void *xbar, void *stream) {
+    return spc5_spmv_transpose_values(A, nullptr, ybar, xbar, stream);
+}
+
+int spc5_spmv_transpose_values(const spc5_matrix *A, const void *values, const void *ybar,
+                               void *xbar, void *stream) {
+    int st = compute_guard(A, {{ybar, A ? A->nrows : 0}, {xbar, A ? A->ncols : 0}});
+    if (st) return st;
+    DeviceGuard g(A->device);
+    hipError_t e = launch_transpose(A, values ? values : A->val, ybar, xbar, (hipStream_t)stream);
+    return e == hipSuccess ? SPC5_OK : hip_fail(e, "spc5_spmv_transpose launch");
+}
+
+int spc5_values_grad(const spc5_matrix *A, const void *ybar, const void *x, void *vbar,
+                     void *stream) {
+    int st = compute_guard(A, {{ybar, A ? A->nrows : 0}, {x, A ? A->ncols : 0}});
+    if (st) return st;
+    if (!vbar && A->nnz) return fail(SPC5_EINVAL, "vbar is NULL");
+    DeviceGuard g(A->device);
+    hipError_t e = launch_values_grad(A, ybar, x, vbar, (hipStream_t)stream);
+    return e == hipSuccess ? SPC5_OK : hip_fail(e, "spc5_values_grad launch");
+}
+
+int spc5_spmm(const spc5_matrix *A, int nrhs, const void *X, void *Y, void *stream) {
+    int st = compute_guard(A, {{X, A ? A->ncols : 0}, {Y, A ? A->nrows : 0}});
+    if (st) return st;
+    if (nrhs < 1 || nrhs > 64) return fail(SPC5_EINVAL, "nrhs must be in 1..64");
+    DeviceGuard g(A->device);
+    hipError_t e = launch_spmm(A, nrhs, X, Y, (hipStream_t)stream);
+    return e == hipSuccess ? SPC5_OK : hip_fail(e, "spc5_spmm launch");
+}
+
+// ---------------------------------------------------------------- CSR
+
+int spc5_csr_create(int64_t nrows, int64_t ncols, const int64_t *rowptr,
+                    const int32_t *colidx, const void *values, spc5_dtype dtype,
+                    spc5_csr **out) {
+    if (!out) return fail(SPC5_EINVAL, "out is NULL");
+    *out = nullptr;
+    int st;
+    if ((st = check_create_args(nrows, ncols, dtype)) != SPC5_OK) return st;
+    int64_t nnz = 0;
+    if ((st = validate_csr(nrows, ncols, rowptr, colidx, values, &nnz)) != SPC5_OK) return st;
+    if (nrows >= ((int64_t)1 << 31) - 1) return fail(SPC5_EUNSUPPORTED, "nrows >= 2^31-1");
+    spc5_csr *A = new (std::nothrow) spc5_csr();
+    if (!A) return fail(SPC5_ENOMEM, "host allocation failed");
+    A->nrows = nrows; A->ncols = ncols; A->nnz = nnz; A->dtype = dtype;
+    hipError_t e = hipGetDevice(&A->device);
+    if (e != hipSuccess) { delete A; return hip_fail(e, "hipGetDevice"); }
+    const int vb = dtype == SPC5_F64 ? 8 : 4;
+    std::vector<int32_t> rp32((size_t)nrows + 1);
+    for (int64_t i = 0; i <= nrows; ++i) rp32[i] = (int32_t)rowptr[i];
+    auto drop = [&]() {
+        if (A->rowptr) (void)hipFree(A->rowptr);
+        if (A->colidx) (void)hipFree(A->colidx);
+        if (A->val) (void)hipFree(A->val);
+        delete A;
+    };
+    if ((e = dmalloc((void **)&A->rowptr, rp32.size() * 4)) != hipSuccess ||
+        (e = dmalloc((void **)&A->colidx, (size_t)nnz * 4)) != hipSuccess ||
+        (e = dmalloc(&A->val, (size_t)nnz * vb)) != hipSuccess) {
+        drop();
+        return hip_fail(e, "allocating device CSR");
+    }
+    if ((e = hipMemcpy(A->rowptr, rp32.data(), rp32.size() * 4, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (nnz > 0 &&
+         ((e = hipMemcpy(A->colidx, colidx, (size_t)nnz * 4, hipMemcpyHostToDevice)) !=
+              hipSuccess ||
+          (e = hipMemcpy(A->val, values, (size_t)nnz * vb, hipMemcpyHostToDevice)) !=
+              hipSuccess))) {
+        drop();
+        return hip_fail(e, "uploading CSR");
+    }
+    A->rpt = default_ppt(nrows ? (double)nnz / (double)nrows : 0.0);
+    *out = A;
+    return SPC5_OK;
+}
+
+void spc5_csr_free(spc5_csr *A) {
+    if (!A) return;
+    DeviceGuard g(A->device);
+    if (A->rowptr) (void)hipFree(A->rowptr);
+    if (A->colidx) (void)hipFree(A->colidx);
+    if (A->val) (void)hipFree(A->val);
+    delete A;
+}
+
+int spc5_csr_spmv(const spc5_csr *A, const void *x, void *y, void *stream) {
+    if (!A) return fail(SPC5_EINVAL, "A is NULL");
+    if ((!x && A->ncols > 0) || (!y && A->nrows > 0)) return fail(SPC5_EINVAL, "NULL vector");
+    DeviceGuard g(A->device);
+    hipError_t e = launch_csr_spmv(A, x, y, (hipStream_t)stream);
+    return e == hipSuccess ? SPC5_OK : hip_fail(e, "spc5_csr_spmv launch");
+}
+
+int64_t spc5_csr_bytes(const spc5_csr *A) {
+    if (!A) return -1;
+    const int64_t vb = A->dtype == SPC5_F64 ? 8 : 4;
+    return vb * A->nnz + 4 * A->nnz + 4 * (A->nrows + 1) + vb * A->ncols + vb * A->nrows;
+}
+
+}  // extern "C"

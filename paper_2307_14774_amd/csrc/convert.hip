@@ -1,0 +1,265 @@
+// CSR -> SPC5 beta(r,c) conversion on the device (Section 2.4 of
+// arXiv 2307.14774).
+//
+// Blocking rule: inside a panel of r rows, a block is anchored at the
+// smallest column not yet covered among the panel's rows and takes, in every
+// row, the nonzeros of columns [anchor, anchor+c).  Each panel is blocked
+// independently by one thread (two passes: count, then fill after an
+// exclusive scan of the per-panel counts gives every panel its first block).
+// A panel's packed values occupy exactly the CSR value range of its rows, so
+// the fill pass writes them at rowptr[first row of the panel] onward without
+// any further scan.
+#include "spc5_internal.h"
+#include "wave.h"
+
+#include <climits>
+#include <vector>
+
+namespace spc5 {
+
+constexpr int kMaxR = 8;
+
+template <bool FILL, typename T, typename MT>
+__global__ __launch_bounds__(256) void k_block_panels(
+    int64_t nrows, int64_t npanels, int r, int c, const int64_t *__restrict__ rowptr,
+    const int32_t *__restrict__ colidx, const T *__restrict__ vin,
+    int64_t *__restrict__ count, const int64_t *__restrict__ bptr,
+    int32_t *__restrict__ bcol, MT *__restrict__ masks, T *__restrict__ vout)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npanels) return;
+    const int64_t row0 = p * r;
+    const int nr = (int)min((int64_t)r, nrows - row0);
+    const int64_t kNone = INT64_MAX;
+    int64_t cur[kMaxR], end[kMaxR], col[kMaxR];
+#pragma unroll
+    for (int i = 0; i < kMaxR; ++i) {
+        cur[i] = i < nr ? rowptr[row0 + i] : 0;
+        end[i] = i < nr ? rowptr[row0 + i + 1] : 0;
+        col[i] = cur[i] < end[i] ? (int64_t)colidx[cur[i]] : kNone;
+    }
+    int64_t nb = 0;
+    const int64_t first = FILL ? bptr[p] : 0;
+    int64_t vo = FILL ? rowptr[row0] : 0;
+    for (;;) {
+        int64_t anchor = kNone;
+#pragma unroll
+        for (int i = 0; i < kMaxR; ++i) anchor = col[i] < anchor ? col[i] : anchor;
+        if (anchor == kNone) break;
+        const int64_t lim = anchor + c;
+        if (FILL) bcol[first + nb] = (int32_t)anchor;
+#pragma unroll
+        for (int i = 0; i < kMaxR; ++i) {
+            unsigned m = 0;
+            while (col[i] < lim) {
+                m |= 1u << (unsigned)(col[i] - anchor);
+                if (FILL) vout[vo++] = vin[cur[i]];
+                ++cur[i];
+                col[i] = cur[i] < end[i] ? (int64_t)colidx[cur[i]] : kNone;
+            }
+            if (FILL && i < r) masks[(first + nb) * r + i] = (MT)m;
+        }
+        ++nb;
+    }
+    if (!FILL) count[p] = nb;
+}
+
+// ---- exclusive scan of int64 counts: out[0..n] with out[n] = total ----------
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;
+constexpr int kScanChunk = kScanThreads * kScanPer;
+
+__device__ int64_t block_excl_scan(int64_t v, int64_t *sh, int64_t *total) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        const int64_t o = t >= d ? sh[t - d] : 0;
+        __syncthreads();
+        sh[t] += o;
+        __syncthreads();
+    }
+    const int64_t incl = sh[t];
+    *total = sh[kScanThreads - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int64_t *in, int64_t n,
+                                                              int64_t *part) {
+    __shared__ int64_t sh[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+    int64_t s = 0;
+    for (int e = 0; e < kScanPer; ++e)
+        if (base + e < n) s += in[base + e];
+    int64_t tot;
+    block_excl_scan(s, sh, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_parts(int64_t *part, int64_t nparts) {
+    __shared__ int64_t sh[kScanThreads];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nparts; base += kScanThreads) {
+        const int64_t idx = base + threadIdx.x;
+        const int64_t v = idx < nparts ? part[idx] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan(v, sh, &tot);
+        if (idx < nparts) part[idx] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int64_t *in, int64_t n,
+                                                             const int64_t *part,
+                                                             int64_t *out) {
+    __shared__ int64_t sh[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+    int64_t s = 0;
+    for (int e = 0; e < kScanPer; ++e)
+        if (base + e < n) s += in[base + e];
+    int64_t tot;
+    int64_t run = part[blockIdx.x] + block_excl_scan(s, sh, &tot);
+    for (int e = 0; e < kScanPer; ++e) {
+        if (base + e < n) {
+            out[base + e] = run;
+            run += in[base + e];
+            if (base + e == n - 1) out[n] = run;
+        }
+    }
+}
+
+// blk_ptr (int32) and the value offset of every panel start.
+__global__ void k_narrow(int64_t npanels, int64_t nrows, int r, const int64_t *bptr64,
+                         const int64_t *rowptr, int32_t *bptr, int32_t *pval) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > npanels) return;
+    bptr[p] = (int32_t)bptr64[p];
+    const int64_t row = p * r < nrows ? p * r : nrows;
+    pval[p] = (int32_t)rowptr[row];
+}
+
+__global__ void k_zero(uint32_t *p, int64_t nwords, uint8_t *tail, int ntail) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nwords) p[i] = 0u;
+    if (i < ntail) tail[i] = 0;
+}
+
+hipError_t zero_fill(void *p, int64_t n, int elem_bytes, hipStream_t s) {
+    const int64_t bytes = n * elem_bytes;
+    if (bytes <= 0) return hipSuccess;
+    const int64_t nwords = bytes / 4;
+    const int ntail = (int)(bytes - nwords * 4);
+    const int64_t work = nwords > ntail ? nwords : ntail;
+    const int64_t grid = (work + 255) / 256;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)grid), dim3(256), 0, s, (uint32_t *)p, nwords,
+                       (uint8_t *)p + nwords * 4, ntail);
+    return hipGetLastError();
+}
+
+static hipError_t excl_scan(const int64_t *in, int64_t n, int64_t *out, hipStream_t s,
+                            int64_t **scratch) {
+    hipError_t e;
+    if (n == 0) return zero_fill(out, 1, 8, s);
+    const int64_t nparts = (n + kScanChunk - 1) / kScanChunk;
+    if ((e = hipMalloc((void **)scratch, (size_t)nparts * 8)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nparts), dim3(kScanThreads), 0, s, in, n,
+                       *scratch);
+    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScanThreads), 0, s, *scratch, nparts);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nparts), dim3(kScanThreads), 0, s, in, n,
+                       *scratch, out);
+    return hipGetLastError();
+}
+
+template <typename T, typename MT>
+static hipError_t launch_block(bool fill, spc5_matrix *A, const int64_t *rowptr,
+                               const int32_t *colidx, const void *vin, int64_t *count,
+                               const int64_t *bptr, hipStream_t s) {
+    const int64_t grid = (A->npanels + 255) / 256;
+    if (grid == 0) return hipSuccess;
+    if (fill)
+        hipLaunchKernelGGL((k_block_panels<true, T, MT>), dim3((unsigned)grid), dim3(256), 0, s,
+                           A->nrows, A->npanels, A->r, A->c, rowptr, colidx, (const T *)vin,
+                           count, bptr, A->blk_col, (MT *)A->masks, (T *)A->val);
+    else
+        hipLaunchKernelGGL((k_block_panels<false, T, MT>), dim3((unsigned)grid), dim3(256), 0,
+                           s, A->nrows, A->npanels, A->r, A->c, rowptr, colidx,
+                           (const T *)vin, count, bptr, (int32_t *)nullptr, (MT *)nullptr,
+                           (T *)nullptr);
+    return hipGetLastError();
+}
+
+static hipError_t launch_block_any(bool fill, spc5_matrix *A, const int64_t *rowptr,
+                                   const int32_t *colidx, const void *vin, int64_t *count,
+                                   const int64_t *bptr, hipStream_t s) {
+    if (A->dtype == SPC5_F64)
+        return A->mask_bytes == 1
+                   ? launch_block<double, uint8_t>(fill, A, rowptr, colidx, vin, count, bptr, s)
+                   : launch_block<double, uint16_t>(fill, A, rowptr, colidx, vin, count, bptr,
+                                                    s);
+    return A->mask_bytes == 1
+               ? launch_block<float, uint8_t>(fill, A, rowptr, colidx, vin, count, bptr, s)
+               : launch_block<float, uint16_t>(fill, A, rowptr, colidx, vin, count, bptr, s);
+}
+
+int convert_on_device(spc5_matrix *A, const int64_t *d_rowptr, const int32_t *d_colidx,
+                      const void *d_values) {
+    hipStream_t s = nullptr;
+    hipError_t e;
+    int64_t *count = nullptr, *bptr64 = nullptr, *scratch = nullptr;
+    int status = SPC5_OK;
+    const int vb = A->dtype == SPC5_F64 ? 8 : 4;
+    auto cleanup = [&]() {
+        if (count) (void)hipFree(count);
+        if (bptr64) (void)hipFree(bptr64);
+        if (scratch) (void)hipFree(scratch);
+    };
+    const size_t np1 = (size_t)A->npanels + 1;
+    if ((e = hipMalloc((void **)&count, np1 * 8)) != hipSuccess ||
+        (e = hipMalloc((void **)&bptr64, np1 * 8)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "allocating conversion scratch");
+    }
+    if ((e = launch_block_any(false, A, d_rowptr, d_colidx, d_values, count, nullptr, s)) !=
+            hipSuccess ||
+        (e = excl_scan(count, A->npanels, bptr64, s, &scratch)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "counting blocks");
+    }
+    int64_t nblocks = 0;
+    if ((e = hipMemcpy(&nblocks, bptr64 + A->npanels, 8, hipMemcpyDeviceToHost)) !=
+        hipSuccess) {
+        cleanup();
+        return hip_fail(e, "reading the block count");
+    }
+    if (nblocks >= ((int64_t)1 << 31)) {
+        cleanup();
+        return fail(SPC5_EUNSUPPORTED, "nblocks = %lld does not fit int32 device indices",
+                    (long long)nblocks);
+    }
+    A->nblocks = nblocks;
+    const size_t nb_alloc = (size_t)(nblocks > 0 ? nblocks : 1);
+    const size_t nnz_alloc = (size_t)(A->nnz > 0 ? A->nnz : 1);
+    if ((e = hipMalloc((void **)&A->blk_ptr, np1 * 4)) != hipSuccess ||
+        (e = hipMalloc((void **)&A->panel_val, np1 * 4)) != hipSuccess ||
+        (e = hipMalloc((void **)&A->blk_col, nb_alloc * 4)) != hipSuccess ||
+        (e = hipMalloc(&A->masks, nb_alloc * A->r * A->mask_bytes)) != hipSuccess ||
+        (e = hipMalloc(&A->val, nnz_alloc * vb)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "allocating SPC5 arrays");
+    }
+    if ((e = launch_block_any(true, A, d_rowptr, d_colidx, d_values, nullptr, bptr64, s)) !=
+        hipSuccess) {
+        cleanup();
+        return hip_fail(e, "filling SPC5 arrays");
+    }
+    hipLaunchKernelGGL(k_narrow, dim3((unsigned)((np1 + 255) / 256)), dim3(256), 0, s,
+                       A->npanels, A->nrows, A->r, bptr64, d_rowptr, A->blk_ptr,
+                       A->panel_val);
+    if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
+        status = hip_fail(e, "finishing the conversion");
+    cleanup();
+    return status;
+}
+
+}  // namespace spc5

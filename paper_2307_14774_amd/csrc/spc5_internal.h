@@ -1,0 +1,64 @@
+// Internal declarations shared by the HIP translation units of libspc5.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "spc5.h"
+
+struct spc5_matrix {
+    int64_t nrows = 0, ncols = 0, nnz = 0, nblocks = 0, npanels = 0;
+    int r = 1, c = 1;
+    spc5_dtype dtype = SPC5_F64;
+    int mask_bytes = 1;
+    int ppt = 1;           // panels per wavefront tile
+    int device = 0;
+    int32_t *blk_ptr = nullptr;    // [npanels+1]
+    int32_t *blk_col = nullptr;    // [nblocks]
+    void *masks = nullptr;         // [nblocks*r], uint8 or uint16
+    void *val = nullptr;           // [nnz]
+    int32_t *panel_val = nullptr;  // [npanels+1], value offset of each panel
+};
+
+struct spc5_csr {
+    int64_t nrows = 0, ncols = 0, nnz = 0;
+    spc5_dtype dtype = SPC5_F64;
+    int rpt = 1;                   // rows per wavefront tile
+    int device = 0;
+    int32_t *rowptr = nullptr;     // [nrows+1]
+    int32_t *colidx = nullptr;     // [nnz]
+    void *val = nullptr;           // [nnz]
+};
+
+namespace spc5 {
+
+// Record a failure for spc5_last_error() and return `status`.
+int fail(int status, const char *fmt, ...);
+// Map a HIP error to SPC5_EDEVICE / SPC5_ENOMEM with a message.
+int hip_fail(hipError_t e, const char *what);
+
+// Default wavefront tile width (in panels) for a mean number of block rows
+// per panel.
+int default_ppt(double blockrows_per_panel);
+
+// Forward product; `val` overrides the matrix's packed values when non-null.
+hipError_t launch_spmv(const spc5_matrix *A, const void *val, const void *x, void *y,
+                       hipStream_t s);
+hipError_t launch_csr_spmv(const spc5_csr *A, const void *x, void *y, hipStream_t s);
+hipError_t launch_spmm(const spc5_matrix *A, int nrhs, const void *X, void *Y,
+                       hipStream_t s);
+hipError_t launch_transpose(const spc5_matrix *A, const void *val, const void *ybar,
+                            void *xbar, hipStream_t s);
+hipError_t launch_values_grad(const spc5_matrix *A, const void *ybar, const void *x,
+                              void *vbar, hipStream_t s);
+
+// CSR -> SPC5 conversion on the device (d_* are device CSR arrays).
+int convert_on_device(spc5_matrix *A, const int64_t *d_rowptr, const int32_t *d_colidx,
+                      const void *d_values);
+
+// Fill `n` elements of a device array with zero using a kernel (safe to
+// record in a graph).
+hipError_t zero_fill(void *p, int64_t n, int elem_bytes, hipStream_t s);
+
+}  // namespace spc5

@@ -1,0 +1,33 @@
+"""Shared helpers of the GPU parity tests: run the HIP path through the C ABI
+and compare with the CPU oracle on the same seeded inputs."""
+import sys
+
+import numpy as np
+
+import oracle
+
+
+def say(msg: str):
+    """Name the case before a GPU step (flushed, so it survives a crash)."""
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def row_error_bound_ok(y, A, x, dtype_eps: float, slack: float = 1.0):
+    """Per-row forward error bound |y_i - exact_i| <= gamma_n sum_j |a_ij x_j|
+    (holds for any summation order, with or without fused multiply-add),
+    with exact_i taken from the FP64 oracle (whose own error is smaller)."""
+    yref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, x)
+    absum = oracle.csr_spmv(A.rowptr, A.colidx, np.abs(A.values), np.abs(x))
+    n = np.diff(A.rowptr).astype(np.float64)
+    gamma = (n + 1) * dtype_eps / (1 - (n + 1) * dtype_eps)
+    # the oracle's own error uses the FP64 unit roundoff
+    g64 = n * 2.0 ** -53 / (1 - n * 2.0 ** -53)
+    bound = slack * (gamma + g64) * absum
+    err = np.abs(np.asarray(y, dtype=np.float64) - yref)
+    bad = np.nonzero(err > bound)[0]
+    return bad
+
+
+def masks_u16(masks: np.ndarray) -> np.ndarray:
+    return masks.astype(np.uint16)

@@ -1,0 +1,99 @@
+"""GPU parity at full benchmark sizes, in the launch configuration bench.py
+times (default schedule): the whole y is compared with the CPU oracle, which
+runs the plain CSR definition in FP64 in well under a few seconds."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import row_error_bound_ok, say
+from paper_2307_14774_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+_cache = {}
+
+
+def workload(name):
+    if name not in _cache:
+        _cache.clear()
+        _cache[name] = {"random10k": lambda: W.random_uniform(10_000, 10, seed=0),
+                        "laplacian2048": lambda: W.laplacian_2d(2048, seed=0),
+                        "fem96": lambda: W.fem_3d(96, seed=0)}[name]()
+    return _cache[name]
+
+
+def check(A, r, c, dev, dtype="float64"):
+    from paper_2307_14774_amd import spc5 as S
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c, dtype)
+    x = torch.from_numpy(A.x).to(dev, tdt)
+    y = M.spmv(x)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    yref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
+    err = oracle.rel_l2(y, yref)
+    M.free()
+    return y, yref, err
+
+
+@pytest.mark.parametrize("name", ["random10k", "laplacian2048"])
+@pytest.mark.parametrize("rc", [(1, 8), (2, 4), (4, 4)], ids=lambda t: "b%d_%d" % t)
+def test_full_size_f64(name, rc, dev):
+    A = workload(name)
+    say(f"full {name} beta{rc} f64")
+    y, yref, err = check(A, *rc, dev)
+    assert err <= 1e-14, err
+    assert row_error_bound_ok(y, A, A.x, 2.0 ** -53).size == 0
+
+
+def test_full_size_laplacian_conversion(dev):
+    from paper_2307_14774_amd import spc5 as S
+    A = workload("laplacian2048")
+    for r, c in [(1, 8), (2, 4), (4, 4)]:
+        say(f"full laplacian conversion beta({r},{c})")
+        M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+        bp, bc, mk, va = M.export()
+        O = oracle.csr_to_spc5(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+        assert np.array_equal(bp, O.blk_ptr) and np.array_equal(bc, O.blk_col)
+        assert np.array_equal(mk.astype(np.uint16), O.masks)
+        assert np.array_equal(va, O.values)
+        N = 2048
+        assert M.info.nblocks == {(1, 8): 3 * N * N - 2 * N, (2, 4): 3 * N * N // 2 - N,
+                                  (4, 4): N * N - N // 2}[(r, c)]
+        M.free()
+
+
+def test_full_size_laplacian_f32(dev):
+    A = workload("laplacian2048")
+    say("full laplacian beta(4,4) f32")
+    _, _, err = check(A, 4, 4, dev, "float32")
+    assert err <= 1e-6, err
+
+
+def test_full_size_laplacian_csr(dev):
+    from paper_2307_14774_amd import spc5 as S
+    A = workload("laplacian2048")
+    say("full laplacian csr f64")
+    M = S.CsrMatrix(A.rowptr, A.colidx, A.values, A.ncols)
+    y = M.spmv(torch.from_numpy(A.x).to(dev)).cpu().numpy()
+    assert oracle.rel_l2(y, oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)) <= 1e-14
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("rc,dtype,tol", [((4, 4), "float64", 1e-14), ((1, 8), "float64", 1e-14),
+                                          ((4, 4), "float32", 1e-6)],
+                         ids=["b4_4-f64", "b1_8-f64", "b4_4-f32"])
+def test_full_size_fem(rc, dtype, tol, dev):
+    A = workload("fem96")
+    say(f"full fem96 beta{rc} {dtype}")
+    _, _, err = check(A, *rc, dev, dtype)
+    assert err <= tol, err

@@ -1,0 +1,297 @@
+"""GPU parity: the HIP library (called through the C ABI) against the CPU
+oracle on the same seeded inputs.
+
+Bars: bit-exact for the conversion (integer/byte work) and for cases whose
+result is unique (integer-valued data, unit vectors, single products);
+relative L2 error <= 1e-14 (FP64) / 1e-6 (FP32, against the FP64 oracle on
+the original FP64 data) plus a per-row forward error bound for sums.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import row_error_bound_ok, say
+from paper_2307_14774_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 8), (2, 4), (4, 4), (1, 16), (2, 8), (4, 8), (8, 8), (8, 4), (3, 5),
+          (1, 1), (5, 16), (7, 3), (6, 12), (2, 2), (1, 4)]
+MAIN = [(1, 8), (2, 4), (4, 4)]
+
+
+def spc5():
+    from paper_2307_14774_amd import spc5 as S
+    return S
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def to_dev(a, dev, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dtype)
+
+
+def small_cases():
+    import test_oracle as T
+    cases = T.edge_cases()
+    cases.append(W.laplacian_2d(37, seed=5))          # ragged: 1369 rows
+    cases.append(W.fem_3d(5, seed=6))
+    cases.append(W.random_uniform(3001, 10, seed=7))
+    cases.append(W.random_sparse(700, 900, 0.02, seed=8))
+    cases.append(W.dense(130, seed=9))
+    # a long panel: rows of 5000 nonzeros (many sweeps per tile)
+    cases.append(W.random_sparse(11, 6000, 0.8, seed=10))
+    return cases
+
+
+CASES = small_cases()
+
+
+def run_spmv(A, r, c, dev, dtype="float64", ppt=None):
+    S = spc5()
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c, dtype)
+    if ppt is not None:
+        M.set_schedule(ppt)
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    x = to_dev(A.x, dev, tdt)
+    y = M.spmv(x)
+    torch.cuda.synchronize()
+    return M, y.cpu().numpy()
+
+
+# ------------------------------------------------------------ conversion
+
+@pytest.mark.parametrize("A", CASES, ids=lambda a: a.name)
+@pytest.mark.parametrize("rc", SHAPES, ids=lambda t: "b%d_%d" % t)
+def test_conversion_bit_exact(A, rc, dev):
+    r, c = rc
+    say(f"conversion {A.name} beta{rc}")
+    S = spc5()
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+    bp, bc, mk, va = M.export()
+    O = oracle.csr_to_spc5(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+    assert M.info.nblocks == O.nblocks and M.info.npanels == O.npanels
+    assert np.array_equal(bp, O.blk_ptr)
+    assert np.array_equal(bc, O.blk_col)
+    assert mk.dtype == (np.uint8 if c <= 8 else np.uint16)
+    assert np.array_equal(mk.astype(np.uint16), O.masks)
+    assert np.array_equal(va.view(np.uint64), O.values.view(np.uint64))
+
+
+# ------------------------------------------------------------ forward
+
+@pytest.mark.parametrize("A", CASES, ids=lambda a: a.name)
+@pytest.mark.parametrize("rc", SHAPES, ids=lambda t: "b%d_%d" % t)
+def test_spmv_f64(A, rc, dev):
+    r, c = rc
+    say(f"spmv f64 {A.name} beta{rc}")
+    _, y = run_spmv(A, r, c, dev)
+    yref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
+    assert oracle.rel_l2(y, yref) <= 1e-14
+    bad = row_error_bound_ok(y, A, A.x, 2.0 ** -53)
+    assert bad.size == 0, f"rows over the error bound: {bad[:10]}"
+
+
+@pytest.mark.parametrize("rc", MAIN + [(8, 8), (3, 5)], ids=lambda t: "b%d_%d" % t)
+@pytest.mark.parametrize("ppt", [1, 2, 7, 64])
+def test_spmv_schedules(rc, ppt, dev):
+    A = W.laplacian_2d(45, seed=11)
+    r, c = rc
+    say(f"spmv schedule ppt={ppt} beta{rc}")
+    _, y = run_spmv(A, r, c, dev, ppt=ppt)
+    yref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
+    assert oracle.rel_l2(y, yref) <= 1e-14
+
+
+@pytest.mark.parametrize("rc", SHAPES, ids=lambda t: "b%d_%d" % t)
+def test_spmv_integer_exact(rc, dev):
+    """Integer data: every partial sum is exact, so any order gives the oracle's
+    result bit for bit, in FP64 and FP32."""
+    r, c = rc
+    A = W.random_sparse(301, 257, 0.08, seed=12, integer=True)
+    say(f"spmv integer beta{rc}")
+    yref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
+    _, y = run_spmv(A, r, c, dev)
+    assert np.array_equal(y, yref)
+    _, y32 = run_spmv(A, r, c, dev, "float32")
+    assert np.array_equal(y32.astype(np.float64), yref)
+
+
+@pytest.mark.parametrize("rc", MAIN, ids=lambda t: "b%d_%d" % t)
+def test_spmv_unit_vectors(rc, dev):
+    r, c = rc
+    A = W.random_sparse(120, 90, 0.1, seed=13)
+    S = spc5()
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+    D = oracle.dense(A.rowptr, A.colidx, A.values, A.ncols)
+    say(f"spmv unit vectors beta{rc}")
+    for j in [0, 1, 7, 8, 45, 88, 89]:
+        e = torch.zeros(A.ncols, dtype=torch.float64, device=dev)
+        e[j] = 1.0
+        y = M.spmv(e).cpu().numpy()
+        assert np.array_equal(y, D[:, j]), j
+
+
+@pytest.mark.parametrize("rc", MAIN, ids=lambda t: "b%d_%d" % t)
+def test_spmv_deterministic(rc, dev):
+    r, c = rc
+    A = W.fem_3d(7, seed=14)
+    say(f"spmv determinism beta{rc}")
+    M, y1 = run_spmv(A, r, c, dev)
+    x = to_dev(A.x, dev)
+    for _ in range(3):
+        y2 = M.spmv(x).cpu().numpy()
+        assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
+
+
+def test_spmv_overwrites_y(dev):
+    A = W.random_sparse(50, 40, 0.05, seed=15)    # has empty rows
+    S = spc5()
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 2, 4)
+    y = torch.full((A.nrows,), float("nan"), dtype=torch.float64, device=dev)
+    M.spmv(to_dev(A.x, dev), y)
+    y = y.cpu().numpy()
+    assert np.all(np.isfinite(y))
+    empty = np.diff(A.rowptr) == 0
+    assert empty.any() and np.all(y[empty] == 0.0)
+    assert oracle.rel_l2(y, oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)) <= 1e-14
+
+
+@pytest.mark.parametrize("A", CASES[8:], ids=lambda a: a.name)
+@pytest.mark.parametrize("rc", MAIN + [(1, 16), (4, 8)], ids=lambda t: "b%d_%d" % t)
+def test_spmv_f32(A, rc, dev):
+    r, c = rc
+    say(f"spmv f32 {A.name} beta{rc}")
+    _, y = run_spmv(A, r, c, dev, "float32")
+    yref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
+    assert oracle.rel_l2(y, yref) <= 1e-6
+    # accumulation error alone: against the FP64 oracle on FP32-rounded data
+    v32 = A.values.astype(np.float32).astype(np.float64)
+    x32 = A.x.astype(np.float32).astype(np.float64)
+    A32 = W.Csr(A.nrows, A.ncols, A.rowptr, A.colidx, v32, x32)
+    bad = row_error_bound_ok(y, A32, x32, 2.0 ** -24)
+    assert bad.size == 0
+
+
+# ------------------------------------------------------------ CSR kernel
+
+@pytest.mark.parametrize("A", CASES, ids=lambda a: a.name)
+def test_csr_kernel(A, dev):
+    S = spc5()
+    say(f"csr kernel {A.name}")
+    M = S.CsrMatrix(A.rowptr, A.colidx, A.values, A.ncols)
+    y = M.spmv(to_dev(A.x, dev)).cpu().numpy()
+    yref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
+    assert oracle.rel_l2(y, yref) <= 1e-14
+    assert row_error_bound_ok(y, A, A.x, 2.0 ** -53).size == 0
+
+
+# ------------------------------------------------------------ backward
+
+@pytest.mark.parametrize("A", CASES[4:], ids=lambda a: a.name)
+@pytest.mark.parametrize("rc", MAIN + [(8, 8), (3, 5), (1, 16)], ids=lambda t: "b%d_%d" % t)
+def test_transpose(A, rc, dev):
+    r, c = rc
+    S = spc5()
+    say(f"transpose {A.name} beta{rc}")
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+    rng = np.random.default_rng(16)
+    w = rng.uniform(-1, 1, A.nrows)
+    xb = M.transpose(to_dev(w, dev)).cpu().numpy()
+    ref = oracle.csr_spmv_t(A.rowptr, A.colidx, A.values, w, A.ncols)
+    assert oracle.rel_l2(xb, ref) <= 1e-14
+    # per-column bound: sum over the column's entries in any order
+    absum = oracle.csr_spmv_t(A.rowptr, A.colidx, np.abs(A.values), np.abs(w), A.ncols)
+    ncol = np.bincount(A.colidx, minlength=A.ncols).astype(np.float64)
+    g = (ncol + 1) * 2.0 ** -52 / (1 - (ncol + 1) * 2.0 ** -52)
+    assert np.all(np.abs(xb - ref) <= g * absum)
+
+
+@pytest.mark.parametrize("rc", MAIN + [(8, 8), (3, 5)], ids=lambda t: "b%d_%d" % t)
+def test_transpose_unit_rows_and_integers(rc, dev):
+    r, c = rc
+    A = W.random_sparse(90, 70, 0.1, seed=17, integer=True)
+    S = spc5()
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+    say(f"transpose exact beta{rc}")
+    for i in [0, 3, 44, 89]:
+        e = np.zeros(A.nrows)
+        e[i] = 1.0
+        row = M.transpose(to_dev(e, dev)).cpu().numpy()
+        assert np.array_equal(row, oracle.csr_spmv_t(A.rowptr, A.colidx, A.values, e, A.ncols))
+    w = np.random.default_rng(3).integers(-6, 7, A.nrows).astype(np.float64)
+    xb = M.transpose(to_dev(w, dev)).cpu().numpy()
+    assert np.array_equal(xb, oracle.csr_spmv_t(A.rowptr, A.colidx, A.values, w, A.ncols))
+
+
+@pytest.mark.parametrize("A", CASES[4:], ids=lambda a: a.name)
+@pytest.mark.parametrize("rc", MAIN + [(3, 5), (8, 16)], ids=lambda t: "b%d_%d" % t)
+def test_values_grad_bit_exact(A, rc, dev):
+    r, c = rc
+    S = spc5()
+    say(f"values grad {A.name} beta{rc}")
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+    w = np.random.default_rng(18).uniform(-1, 1, A.nrows)
+    g = M.values_grad(to_dev(w, dev), to_dev(A.x, dev)).cpu().numpy()
+    O = oracle.csr_to_spc5(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+    ref = oracle.spc5_values_grad(O, w, A.x)
+    assert np.array_equal(g.view(np.uint64), ref.view(np.uint64))
+
+
+def test_spmv_values_override(dev):
+    A = W.laplacian_2d(30, seed=19)
+    S = spc5()
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 2, 4)
+    O = oracle.csr_to_spc5(A.rowptr, A.colidx, A.values, A.ncols, 2, 4)
+    theta = np.random.default_rng(20).uniform(-1, 1, A.nnz)
+    O.values = theta
+    y = M.spmv_values(to_dev(theta, dev), to_dev(A.x, dev)).cpu().numpy()
+    yref = oracle.spc5_spmv(O, A.x)
+    assert oracle.rel_l2(y, yref) <= 1e-14
+
+
+# ------------------------------------------------------------ SpMM
+
+@pytest.mark.parametrize("A", [CASES[-6], CASES[-5], CASES[-2]], ids=lambda a: a.name)
+@pytest.mark.parametrize("rc", MAIN + [(8, 8)], ids=lambda t: "b%d_%d" % t)
+@pytest.mark.parametrize("k", [1, 3, 4, 16, 21])
+def test_spmm(A, rc, k, dev):
+    r, c = rc
+    S = spc5()
+    say(f"spmm {A.name} beta{rc} k={k}")
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+    X = np.random.default_rng(21).uniform(-1, 1, (A.ncols, k))
+    Y = M.spmm(to_dev(X, dev)).cpu().numpy()
+    ref = oracle.csr_spmm(A.rowptr, A.colidx, A.values, X)
+    assert oracle.rel_l2(Y, ref) <= 1e-14
+
+
+# ------------------------------------------------------------ errors
+
+def test_alloc_failure_reports_enomem(dev, monkeypatch):
+    S = spc5()
+    A = W.random_sparse(10, 10, 0.3, seed=22)
+    monkeypatch.setenv("SPC5_TEST_FAIL_ALLOC", "1")
+    with pytest.raises(S.Spc5Error) as ei:
+        S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 2, 4)
+    assert ei.value.status == -3
+    monkeypatch.delenv("SPC5_TEST_FAIL_ALLOC")
+    S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 2, 4)
+
+
+def test_binding_rejects_wrong_tensors(dev):
+    S = spc5()
+    A = W.random_sparse(10, 12, 0.3, seed=23)
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 2, 4)
+    with pytest.raises(TypeError):
+        M.spmv(torch.zeros(12, dtype=torch.float32, device=dev))
+    with pytest.raises(ValueError):
+        M.spmv(torch.zeros(11, dtype=torch.float64, device=dev))
+    with pytest.raises(TypeError):
+        M.spmv(torch.zeros(12, dtype=torch.float64))
