@@ -108,6 +108,51 @@ def cpu_baseline(A, rc, budget_s=10.0):
                       f"(beta{rc}, FP64, single thread, {dt:.1f} s)"}
 
 
+def fem_extras(dev):
+    """3D 3-dof 27-point FEM-like matrix (96^3 nodes, 210.5 M nonzeros): FP64
+    and FP32 beta(4,4) and beta(1,8), plain CSR FP64; FP32 error against the
+    FP64 oracle on the original FP64 data."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2307_14774_amd import spc5
+    from paper_2307_14774_amd import workloads as W
+    log("generating the FEM workload")
+    A = W.fem_3d(96, seed=0)
+    yref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
+    res = {"nrows": A.nrows, "nnz": A.nnz}
+    for dt, tdt in (("float64", torch.float64), ("float32", torch.float32)):
+        x = torch.from_numpy(A.x).to(dev, tdt)
+        y = torch.empty(A.nrows, dtype=tdt, device=dev)
+        shapes = [(4, 4), (1, 8), (2, 4)] if dt == "float64" else [(4, 4), (4, 8), (1, 16)]
+        for rc in shapes:
+            log(f"FEM {dt} beta{rc}")
+            M = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, *rc, dt)
+            _, ms = time_launches(lambda: M.spmv(x, y), 30, 5)
+            avg = float(np.mean(ms)) * 1e-3
+            nb = M.info.spmv_bytes
+            res[f"{dt} beta({rc[0]},{rc[1]})"] = {
+                "gflops": round(2.0 * A.nnz / avg / 1e9, 1), "launch_us": round(avg * 1e6, 1),
+                "gbs": round(nb / avg / 1e9, 1), "frac_hbm": round(nb / avg / 1e9 / PEAK_HBM_GBS, 4),
+                "rel_l2_vs_fp64_oracle": oracle.rel_l2(y.cpu().numpy(), yref),
+                "kernel": M.kernel, "fill": round(M.info.fill, 4)}
+            M.free()
+    log("FEM plain CSR fp64")
+    C = spc5.CsrMatrix(A.rowptr, A.colidx, A.values, A.ncols)
+    x = torch.from_numpy(A.x).to(dev)
+    y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+    _, ms = time_launches(lambda: C.spmv(x, y), 30, 5)
+    avg = float(np.mean(ms)) * 1e-3
+    res["float64 csr"] = {"gflops": round(2.0 * A.nnz / avg / 1e9, 1),
+                          "launch_us": round(avg * 1e6, 1),
+                          "gbs": round(C.spmv_bytes / avg / 1e9, 1),
+                          "frac_hbm": round(C.spmv_bytes / avg / 1e9 / PEAK_HBM_GBS, 4),
+                          "rel_l2_vs_fp64_oracle": oracle.rel_l2(y.cpu().numpy(), yref)}
+    C.free()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +225,13 @@ def main():
         "parity_rel_l2": prim["rel_l2"],
     }
     if not args.no_extras:
+        other = "sweep" if M.kernel == "rows" else "rows"
+        log(f"timing the {other} kernel on beta{rc}")
+        M.set_schedule(other)
+        alt = measure(M, 50, 5, nbytes)[0]
+        M.set_schedule("auto")
+        out["kernels"] = {M.kernel: prim, other: alt}
+        prim["kernel"] = M.kernel
         formats = {f"beta({rc[0]},{rc[1]})": prim}
         for (r, c) in [(1, 8), (2, 4), (4, 4), (8, 8), (1, 16), (2, 8), (4, 8)]:
             if (r, c) == rc:
@@ -188,6 +240,7 @@ def main():
             M2 = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c)
             formats[f"beta({r},{c})"] = measure(M2, 50, 5, M2.info.spmv_bytes)[0]
             formats[f"beta({r},{c})"]["fill"] = round(M2.info.fill, 4)
+            formats[f"beta({r},{c})"]["kernel"] = M2.kernel
             M2.free()
         log("timing plain CSR")
         C = spc5.CsrMatrix(A.rowptr, A.colidx, A.values, A.ncols)
@@ -201,7 +254,10 @@ def main():
         del scratch
         out["formats"] = formats
         out["flushed"] = flushed
+
         out["speedup_vs_csr"] = round(formats["csr"]["launch_us"] / prim["launch_us"], 3)
+    if not args.no_extras and args.workload == "laplacian":
+        out["fem"] = fem_extras(dev)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(A, rc, args.cpu_budget)

@@ -68,9 +68,10 @@ typedef struct {
     int32_t r, c;
     int32_t dtype;            /* spc5_dtype */
     int32_t mask_bytes;       /* 1 (c <= 8) or 2 (c > 8) */
-    int32_t panels_per_tile;  /* current schedule: panels handled by one wavefront */
-    int32_t reserved;
-    int64_t ntiles;           /* wavefront tiles of one forward launch */
+    int32_t panels_per_tile;  /* sweep kernel: panels handled by one wavefront */
+    int32_t kernel;           /* spc5_kernel in use for the forward product */
+    int64_t ntiles;           /* wavefronts of one forward launch */
+    int64_t max_panel_blocks; /* longest panel, in blocks */
     double fill;              /* nnz / (nblocks * r * c), Table 1's block filling */
     int64_t spmv_bytes;       /* algorithmic bytes moved by one y = A x:
                                  values + anchors + masks + blk_ptr + x + y */
@@ -112,10 +113,30 @@ int spc5_get_info(const spc5_matrix *A, spc5_info *out);
 int spc5_export(const spc5_matrix *A, int64_t *blk_ptr, int32_t *blk_col,
                 void *masks, void *values);
 
-/* Schedule: number of consecutive panels one wavefront handles
- * (1..64; 0 restores the default chosen from the mean block rows per panel).
- * Not safe to call while compute calls on A are in flight. */
-int spc5_set_schedule(spc5_matrix *A, int panels_per_tile);
+/* Forward-kernel choice.
+ *  SPC5_KERNEL_STAGED: one wavefront per tile of consecutive panels; the
+ *                     tile's packed values, masks and anchors are pulled into
+ *                     LDS with 16-byte coalesced loads, a wavefront scan gives
+ *                     every block its value offset, then lanes walk the rows
+ *                     of the tile (split over sub-lanes for long panels)
+ *                     and gather x.  The default.
+ *  SPC5_KERNEL_ROWS:  one lane per panel row; the lane walks the blocks of
+ *                     its panel (r lanes share a panel), no cross-lane
+ *                     reduction.  Best for short and regular panels.
+ *  SPC5_KERNEL_SWEEP: one wavefront per tile of consecutive panels, one lane
+ *                     per block row, segmented wavefront reduction.  Handles
+ *                     panels of any length evenly.
+ *  SPC5_KERNEL_AUTO:  chosen at conversion from the panel length statistics. */
+typedef enum {
+    SPC5_KERNEL_AUTO = 0, SPC5_KERNEL_ROWS = 1, SPC5_KERNEL_SWEEP = 2, SPC5_KERNEL_STAGED = 3
+} spc5_kernel;
+
+/* Schedule of the forward product: kernel choice and, for the sweep and
+ * staged kernels, the number of consecutive panels one wavefront handles
+ * (1..64, at most 64/r for the staged kernel; 0 = default from the mean panel
+ * length).  Not safe to call while compute calls
+ * on A are in flight. */
+int spc5_set_schedule(spc5_matrix *A, int kernel, int panels_per_tile);
 
 /* ---------------------------------------------------------------- compute */
 

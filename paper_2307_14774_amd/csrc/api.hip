@@ -40,6 +40,30 @@ int default_ppt(double blockrows_per_panel) {
     return (int)std::max(1.0, std::min(64.0, p));
 }
 
+// The staged and row kernels gather x through a raw buffer descriptor,
+// whose byte offsets must stay below 2^31.
+bool x_fits_buffer(const spc5_matrix *A) {
+    return A->ncols * (A->dtype == SPC5_F64 ? 8 : 4) <= 0x7FFFFFF0LL;
+}
+
+int auto_kernel(const spc5_matrix *A) {
+    // The staged kernel needs every panel to fit one LDS staging window;
+    // matrices with a longer panel use the sweep kernel (one lane per block
+    // row, segmented reduction), which takes panels of any length.
+    // beta(1,c): one row per block, no x window to share; the sweep kernel
+    // handles it as well or better
+    return A->staged_ok && x_fits_buffer(A) && A->r > 1 ? SPC5_KERNEL_STAGED
+                                                        : SPC5_KERNEL_SWEEP;
+}
+
+// Lanes per row of the CSR-vector comparison kernel: the power of two
+// nearest the mean row length, within 1..64.
+static int csr_group(double mean_row) {
+    int g = 1;
+    while (g < 64 && g * 2 <= mean_row * 1.5) g *= 2;
+    return g;
+}
+
 // Test hook: SPC5_TEST_FAIL_ALLOC=1 makes every device allocation of the
 // creation calls fail, to exercise the SPC5_ENOMEM path.
 static bool alloc_fail_hook() {
@@ -128,6 +152,9 @@ static void free_matrix(spc5_matrix *A) {
     if (A->masks) (void)hipFree(A->masks);
     if (A->val) (void)hipFree(A->val);
     if (A->panel_val) (void)hipFree(A->panel_val);
+    if (A->tile_p) (void)hipFree(A->tile_p);
+    if (A->tile_b) (void)hipFree(A->tile_b);
+    if (A->tile_v) (void)hipFree(A->tile_v);
     delete A;
 }
 
@@ -192,6 +219,8 @@ int csr_to_spc5(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32
     drop();
     if (st != SPC5_OK) { free_matrix(A); return st; }
     A->ppt = default_ppt(npanels ? (double)A->nblocks * r / (double)npanels : 0.0);
+    if ((st = build_staged_schedule(A, 0)) != SPC5_OK) { free_matrix(A); return st; }
+    A->kernel = auto_kernel(A);
     *out = A;
     return SPC5_OK;
 }
@@ -204,8 +233,12 @@ int spc5_get_info(const spc5_matrix *A, spc5_info *out) {
     out->nrows = A->nrows; out->ncols = A->ncols; out->nnz = A->nnz;
     out->nblocks = A->nblocks; out->npanels = A->npanels;
     out->r = A->r; out->c = A->c; out->dtype = A->dtype; out->mask_bytes = A->mask_bytes;
-    out->panels_per_tile = A->ppt;
-    out->ntiles = (A->npanels + A->ppt - 1) / A->ppt;
+    out->panels_per_tile = A->kernel == SPC5_KERNEL_STAGED ? A->sppt : A->ppt;
+    out->kernel = A->kernel;
+    out->max_panel_blocks = A->max_panel_blocks;
+    out->ntiles = A->kernel == SPC5_KERNEL_ROWS ? (A->npanels + 64 / A->r - 1) / (64 / A->r)
+                  : A->kernel == SPC5_KERNEL_STAGED ? A->ntiles_staged
+                                                    : (A->npanels + A->ppt - 1) / A->ppt;
     out->fill = A->nblocks ? (double)A->nnz / ((double)A->nblocks * A->r * A->c) : 0.0;
     const int64_t vb = A->dtype == SPC5_F64 ? 8 : 4;
     out->spmv_bytes = vb * A->nnz + 4 * A->nblocks + (int64_t)A->r * A->mask_bytes * A->nblocks +
@@ -243,9 +276,20 @@ int spc5_export(const spc5_matrix *A, int64_t *blk_ptr, int32_t *blk_col, void *
     return SPC5_OK;
 }
 
-int spc5_set_schedule(spc5_matrix *A, int ppt) {
+int spc5_set_schedule(spc5_matrix *A, int kernel, int ppt) {
     if (!A) return fail(SPC5_EINVAL, "A is NULL");
+    if (kernel < SPC5_KERNEL_AUTO || kernel > SPC5_KERNEL_STAGED)
+        return fail(SPC5_EINVAL, "unknown kernel %d", kernel);
     if (ppt < 0 || ppt > 64) return fail(SPC5_EINVAL, "panels_per_tile must be in 0..64");
+    if (kernel == SPC5_KERNEL_STAGED && !A->staged_ok)
+        return fail(SPC5_EUNSUPPORTED, "a panel is longer than the staged kernel's window");
+    if ((kernel == SPC5_KERNEL_STAGED || kernel == SPC5_KERNEL_ROWS) && !x_fits_buffer(A))
+        return fail(SPC5_EUNSUPPORTED, "x exceeds 2 GiB: only the sweep kernel applies");
+    A->kernel = kernel == SPC5_KERNEL_AUTO ? auto_kernel(A) : kernel;
+    if (A->kernel == SPC5_KERNEL_STAGED) {
+        DeviceGuard g(A->device);
+        return build_staged_schedule(A, ppt);
+    }
     A->ppt = ppt ? ppt
                  : default_ppt(A->npanels ? (double)A->nblocks * A->r / (double)A->npanels : 0.0);
     return SPC5_OK;
@@ -353,6 +397,7 @@ int spc5_csr_create(int64_t nrows, int64_t ncols, const int64_t *rowptr,
         return hip_fail(e, "uploading CSR");
     }
     A->rpt = default_ppt(nrows ? (double)nnz / (double)nrows : 0.0);
+    A->group = csr_group(nrows ? (double)nnz / (double)nrows : 1.0);
     *out = A;
     return SPC5_OK;
 }

@@ -139,6 +139,11 @@ __global__ void k_narrow(int64_t npanels, int64_t nrows, int r, const int64_t *b
     pval[p] = (int32_t)rowptr[row];
 }
 
+__global__ void k_max(const int64_t *in, int64_t n, unsigned long long *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicMax(out, (unsigned long long)in[i]);
+}
+
 __global__ void k_zero(uint32_t *p, int64_t nwords, uint8_t *tail, int ntail) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nwords) p[i] = 0u;
@@ -157,8 +162,8 @@ hipError_t zero_fill(void *p, int64_t n, int elem_bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-static hipError_t excl_scan(const int64_t *in, int64_t n, int64_t *out, hipStream_t s,
-                            int64_t **scratch) {
+hipError_t excl_scan_i64(const int64_t *in, int64_t n, int64_t *out, hipStream_t s,
+                         int64_t **scratch) {
     hipError_t e;
     if (n == 0) return zero_fill(out, 1, 8, s);
     const int64_t nparts = (n + kScanChunk - 1) / kScanChunk;
@@ -222,16 +227,27 @@ int convert_on_device(spc5_matrix *A, const int64_t *d_rowptr, const int32_t *d_
     }
     if ((e = launch_block_any(false, A, d_rowptr, d_colidx, d_values, count, nullptr, s)) !=
             hipSuccess ||
-        (e = excl_scan(count, A->npanels, bptr64, s, &scratch)) != hipSuccess) {
+        (e = excl_scan_i64(count, A->npanels, bptr64, s, &scratch)) != hipSuccess) {
         cleanup();
         return hip_fail(e, "counting blocks");
     }
+    // longest panel (for the kernel choice): reuse the first partial slot
+    unsigned long long *dmax = (unsigned long long *)scratch;
+    if (A->npanels > 0) {
+        if ((e = zero_fill(dmax, 1, 8, s)) != hipSuccess) { cleanup(); return hip_fail(e, "max"); }
+        hipLaunchKernelGGL(k_max, dim3((unsigned)((A->npanels + 255) / 256)), dim3(256), 0, s,
+                           count, A->npanels, dmax);
+    }
     int64_t nblocks = 0;
+    unsigned long long maxb = 0;
     if ((e = hipMemcpy(&nblocks, bptr64 + A->npanels, 8, hipMemcpyDeviceToHost)) !=
-        hipSuccess) {
+            hipSuccess ||
+        (A->npanels > 0 &&
+         (e = hipMemcpy(&maxb, dmax, 8, hipMemcpyDeviceToHost)) != hipSuccess)) {
         cleanup();
         return hip_fail(e, "reading the block count");
     }
+    A->max_panel_blocks = (int64_t)maxb;
     if (nblocks >= ((int64_t)1 << 31)) {
         cleanup();
         return fail(SPC5_EUNSUPPORTED, "nblocks = %lld does not fit int32 device indices",
@@ -240,11 +256,13 @@ int convert_on_device(spc5_matrix *A, const int64_t *d_rowptr, const int32_t *d_
     A->nblocks = nblocks;
     const size_t nb_alloc = (size_t)(nblocks > 0 ? nblocks : 1);
     const size_t nnz_alloc = (size_t)(A->nnz > 0 ? A->nnz : 1);
-    if ((e = hipMalloc((void **)&A->blk_ptr, np1 * 4)) != hipSuccess ||
-        (e = hipMalloc((void **)&A->panel_val, np1 * 4)) != hipSuccess ||
-        (e = hipMalloc((void **)&A->blk_col, nb_alloc * 4)) != hipSuccess ||
-        (e = hipMalloc(&A->masks, nb_alloc * A->r * A->mask_bytes)) != hipSuccess ||
-        (e = hipMalloc(&A->val, nnz_alloc * vb)) != hipSuccess) {
+    // kPad trailing bytes: the staged kernel reads whole 16-byte vectors, so
+    // the last vector of an array may extend past its last element
+    if ((e = hipMalloc((void **)&A->blk_ptr, np1 * 4 + kPad)) != hipSuccess ||
+        (e = hipMalloc((void **)&A->panel_val, np1 * 4 + kPad)) != hipSuccess ||
+        (e = hipMalloc((void **)&A->blk_col, nb_alloc * 4 + kPad)) != hipSuccess ||
+        (e = hipMalloc(&A->masks, nb_alloc * A->r * A->mask_bytes + kPad)) != hipSuccess ||
+        (e = hipMalloc(&A->val, nnz_alloc * vb + kPad)) != hipSuccess) {
         cleanup();
         return hip_fail(e, "allocating SPC5 arrays");
     }

@@ -12,19 +12,28 @@ struct spc5_matrix {
     int r = 1, c = 1;
     spc5_dtype dtype = SPC5_F64;
     int mask_bytes = 1;
-    int ppt = 1;           // panels per wavefront tile
+    int ppt = 1;           // panels per wavefront tile (sweep kernel)
+    int sppt = 1;          // panels per wavefront tile (staged kernel)
+    int kernel = SPC5_KERNEL_ROWS;   // forward kernel in use (never AUTO)
+    int64_t max_panel_blocks = 0;
     int device = 0;
     int32_t *blk_ptr = nullptr;    // [npanels+1]
     int32_t *blk_col = nullptr;    // [nblocks]
     void *masks = nullptr;         // [nblocks*r], uint8 or uint16
     void *val = nullptr;           // [nnz]
     int32_t *panel_val = nullptr;  // [npanels+1], value offset of each panel
+    // staged-kernel tile schedule: first panel / block / value of each tile
+    int32_t *tile_p = nullptr, *tile_b = nullptr, *tile_v = nullptr;   // [ntiles_staged+1]
+    int64_t ntiles_staged = 0;
+    int max_tile_values = 0;       // largest tile, in values
+    bool staged_ok = false;        // every panel fits one staging window
 };
 
 struct spc5_csr {
     int64_t nrows = 0, ncols = 0, nnz = 0;
     spc5_dtype dtype = SPC5_F64;
-    int rpt = 1;                   // rows per wavefront tile
+    int rpt = 1;                   // rows per wavefront tile (segmented kernel)
+    int group = 0;                 // lanes per row of the CSR-vector kernel (0: segmented)
     int device = 0;
     int32_t *rowptr = nullptr;     // [nrows+1]
     int32_t *colidx = nullptr;     // [nnz]
@@ -32,6 +41,9 @@ struct spc5_csr {
 };
 
 namespace spc5 {
+
+// Trailing padding (bytes) of every device array of a matrix.
+constexpr size_t kPad = 64;
 
 // Record a failure for spc5_last_error() and return `status`.
 int fail(int status, const char *fmt, ...);
@@ -41,10 +53,20 @@ int hip_fail(hipError_t e, const char *what);
 // Default wavefront tile width (in panels) for a mean number of block rows
 // per panel.
 int default_ppt(double blockrows_per_panel);
+// Forward kernel picked from the panel statistics of A.
+int auto_kernel(const spc5_matrix *A);
 
 // Forward product; `val` overrides the matrix's packed values when non-null.
 hipError_t launch_spmv(const spc5_matrix *A, const void *val, const void *x, void *y,
                        hipStream_t s);
+hipError_t launch_spmv_staged(const spc5_matrix *A, const void *val, const void *x, void *y,
+                              hipStream_t s, int remap);
+// (Re)build the staged kernel's tile schedule with at most ppw panels per tile
+// (0: as many as one workgroup has rows for).
+int build_staged_schedule(spc5_matrix *A, int ppw);
+hipError_t excl_scan_i64(const int64_t *in, int64_t n, int64_t *out, hipStream_t s,
+                         int64_t **scratch);
+int remap_enabled();
 hipError_t launch_csr_spmv(const spc5_csr *A, const void *x, void *y, hipStream_t s);
 hipError_t launch_spmm(const spc5_matrix *A, int nrhs, const void *X, void *Y,
                        hipStream_t s);

@@ -1,0 +1,515 @@
+// STAGED forward kernel: y = A x over SPC5 beta(r,c) storage, one 256-thread
+// workgroup per tile of consecutive panels, the tile streamed through LDS.
+//
+// Why this shape.  On gfx950 a product over short rows is bound by the number
+// of vector memory instructions (each costs the address unit about the same
+// whatever its width) and by the latency of its dependent accesses.  So:
+//
+//  1. stage: the tile's packed values, row masks, anchors and panel bounds
+//     are contiguous ranges; the workgroup copies them into LDS with 16-byte
+//     vector loads (4 KiB per workgroup instruction), all issued before the
+//     first store;
+//  2. block value offsets: each block's value count is the popcount of its r
+//     row masks; a workgroup prefix scan turns the counts into offsets -- the
+//     parallel form of the running value index of Algorithm 1;
+//  3. single x load per block: one thread per block gathers x[anchor + k] for
+//     every column k that some row of the block uses (the union of its row
+//     masks) into LDS.  This is the single-x-load scheme of Section 3.1: the
+//     r rows of a block share one load of the x window, so x loads scale with
+//     blocks, not with nonzeros;
+//  4. rows: thread = (panel, sub-lane, row); it walks every S-th block of its
+//     panel, takes its row mask and the popcount of the lower rows' masks
+//     (its offset inside the block), and for every set bit k multiplies the
+//     next packed value by the block's x entry k, both from LDS;
+//  5. a butterfly over the S sub-lanes, one store per row.
+//
+// Tiles come from a schedule built at conversion (at most 256/r panels, VT
+// values and BT blocks per tile); a matrix with a single panel larger than a
+// tile uses the sweep kernel.  No atomics: results are reproducible bit for
+// bit.
+#include "spc5_internal.h"
+#include "wave.h"
+
+#include <algorithm>
+#include <climits>
+#include <cstdlib>
+
+namespace spc5 {
+
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+constexpr int kWG = 256;   // threads per workgroup (4 wavefronts)
+
+template <typename T, int R, int C, int NVG = 4>
+struct StreamCfg {
+    using MT = typename MaskOf<C>::type;
+    static constexpr int MB = (int)sizeof(MT);
+    // LDS bytes for the values of one tile: NVG 16-byte vectors per thread
+    static constexpr int VBYTES = 4096 * NVG;
+    static constexpr int VT = (16384 - 16) / (int)sizeof(T);           // schedule cap
+    static constexpr int BT0 = 8192 / (C * (int)sizeof(T));
+    static constexpr int BT = BT0 < 256 ? BT0 : 256;                   // blocks per tile
+    static constexpr int PPW = kWG / R;                                // panels per tile
+    static constexpr int VVEC = VBYTES / 16;
+    static constexpr int MVEC = (BT * R * MB + 30) / 16;
+    static constexpr int CVEC = (BT * 4 + 30) / 16;
+    static constexpr int PVEC = ((PPW + 1) * 4 + 30) / 16;
+    static constexpr int NV = VVEC / kWG;                              // vectors per thread
+    static constexpr int NM = (MVEC + kWG - 1) / kWG;
+    static constexpr int NC = (CVEC + kWG - 1) / kWG;
+    static constexpr int NP = (PVEC + kWG - 1) / kWG;
+    static constexpr int U = R * C <= 16 ? 4 : 2;                      // blocks per step
+};
+
+// Tile capacities for a matrix (must match StreamCfg).
+void staged_caps(const spc5_matrix *A, int *vt, int *bt, int *ppw) {
+    const int sz = A->dtype == SPC5_F64 ? 8 : 4;
+    const int cm = A->c <= 4 ? 4 : (A->c <= 8 ? 8 : 16);
+    *vt = (16384 - 16) / sz;
+    *bt = std::min(256, 8192 / (cm * sz));
+    *ppw = kWG / A->r;
+}
+
+// Row masks of block t in LDS (bytes of block t start at t*R*MB): the mask of
+// row i, the popcount of the rows below i and of the whole block.
+template <int R, int C>
+__device__ __forceinline__ void lds_block_masks(const uint8_t *sm, int t, int i, unsigned &m,
+                                                int &pre, int &tot) {
+    using MT = typename MaskOf<C>::type;
+    constexpr int MB = (int)sizeof(MT);
+    constexpr int WB = R * MB;
+    if constexpr (WB == 1 || WB == 2 || WB == 4 || WB == 8) {
+        uint64_t w;
+        if constexpr (WB == 1) w = sm[t];
+        else if constexpr (WB == 2) w = *(const uint16_t *)(sm + 2 * t);
+        else if constexpr (WB == 4) w = *(const uint32_t *)(sm + 4 * t);
+        else w = *(const uint64_t *)(sm + 8 * t);
+        const int sh = i * 8 * MB;
+        m = (unsigned)(w >> sh) & ((1u << (8 * MB)) - 1u);
+        pre = __popcll(sh ? (w & ((1ull << sh) - 1ull)) : 0ull);
+        tot = __popcll(w);
+    } else {
+        m = 0;
+        pre = 0;
+        tot = 0;
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            unsigned mr;
+            if constexpr (MB == 1) mr = sm[t * R + rr];
+            else mr = ((const uint16_t *)sm)[t * R + rr];
+            const int pc = __popc(mr);
+            pre += rr < i ? pc : 0;
+            m = rr == i ? mr : m;
+            tot += pc;
+        }
+    }
+}
+
+// Union of the r row masks of block t (the columns the block touches).
+template <int R, int C>
+__device__ __forceinline__ unsigned lds_block_union(const uint8_t *sm, int t) {
+    using MT = typename MaskOf<C>::type;
+    constexpr int MB = (int)sizeof(MT);
+    unsigned u = 0;
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+        if constexpr (MB == 1) u |= sm[t * R + rr];
+        else u |= ((const uint16_t *)sm)[t * R + rr];
+    }
+    return u;
+}
+
+// A contiguous byte range of global memory, as 16-byte vectors from an
+// aligned base.
+struct Range16 {
+    const v4u *src;
+    int n;       // vectors
+    int skew;    // bytes from the aligned base to the first wanted byte
+};
+
+__device__ __forceinline__ Range16 range16(const void *base, int64_t byte0, int64_t byte1) {
+    const int64_t a0 = byte0 & ~(int64_t)15;
+    Range16 r;
+    r.src = (const v4u *)((const char *)base + a0);
+    r.n = byte1 > byte0 ? (int)((byte1 - a0 + 15) >> 4) : 0;
+    r.skew = (int)(byte0 - a0);
+    return r;
+}
+
+// Register stage of up to NVMAX vectors per thread.  issue(): G unconditional
+// loads (indices clamped into the range), G the smallest power of two (or
+// NVMAX) covering the range, so the loads are straight-line code and all in
+// flight together; commit(): the matching LDS stores.
+template <int NVMAX>
+struct RegStage {
+    v4u r[NVMAX];
+
+    template <int G>
+    __device__ __forceinline__ void issue_g(const Range16 &q) {
+        const int th = threadIdx.x;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int v = th + kWG * g;
+            r[g] = q.src[v < q.n ? v : q.n - 1];
+        }
+    }
+    __device__ __forceinline__ void issue(const Range16 &q) {
+        if (q.n <= 0) return;
+        if (q.n <= kWG) issue_g<1>(q);
+        else if (NVMAX >= 2 && q.n <= 2 * kWG) issue_g<(NVMAX >= 2 ? 2 : 1)>(q);
+        else if (NVMAX >= 4 && q.n <= 4 * kWG) issue_g<(NVMAX >= 4 ? 4 : 1)>(q);
+        else issue_g<NVMAX>(q);
+    }
+    __device__ __forceinline__ void commit(v4u *dst, const Range16 &q) const {
+        const int th = threadIdx.x;
+#pragma unroll
+        for (int g = 0; g < NVMAX; ++g) {
+            const int v = th + kWG * g;
+            if (v < q.n) dst[v] = r[g];
+        }
+    }
+};
+
+template <typename T, int R, int C, int NVG>
+struct TileStage {
+    using Cfg = StreamCfg<T, R, C, NVG>;
+    Range16 qv, qm, qc, qp;
+    RegStage<Cfg::NV> rv;
+    RegStage<Cfg::NM> rm;
+    RegStage<Cfg::NC> rc;
+    RegStage<Cfg::NP> rp;
+
+    // All NV + NM + NC + NP loads, unconditionally (indices clamped): a fixed
+    // count keeps the compiler's in-order load counters exact, so waiting for
+    // later loads of the current tile never waits for this prefetch.
+    __device__ __forceinline__ void issue(int p0, int p1, int b0, int b1, int v0, int v1,
+                                          const T *val, const void *masks, const int32_t *blk_col,
+                                          const int32_t *blk_ptr) {
+        qv = range16(val, (int64_t)v0 * (int64_t)sizeof(T), (int64_t)v1 * (int64_t)sizeof(T));
+        qm = range16(masks, (int64_t)b0 * R * Cfg::MB, (int64_t)b1 * R * Cfg::MB);
+        qc = range16(blk_col, (int64_t)b0 * 4, (int64_t)b1 * 4);
+        qp = range16(blk_ptr, (int64_t)p0 * 4, (int64_t)(p1 + 1) * 4);
+        fixed(rv, qv);
+        fixed(rm, qm);
+        fixed(rc, qc);
+        fixed(rp, qp);
+    }
+    template <int N>
+    __device__ __forceinline__ static void fixed(RegStage<N> &st, const Range16 &q) {
+        const int th = threadIdx.x;
+        const int nmax = q.n > 0 ? q.n - 1 : 0;
+#pragma unroll
+        for (int g = 0; g < N; ++g) {
+            const int v = th + kWG * g;
+            st.r[g] = q.src[v < nmax ? v : nmax];
+        }
+    }
+};
+
+template <typename T, int R, int C, int NVG>
+__global__ __launch_bounds__(kWG) void k_spmv_stream(
+    int64_t nrows, int64_t ncols, int64_t ntiles, int tiles_per_wg, int64_t nwg, int remap,
+    const int32_t *__restrict__ tile_p, const int32_t *__restrict__ tile_b,
+    const int32_t *__restrict__ tile_v, const int32_t *__restrict__ blk_ptr,
+    const int32_t *__restrict__ blk_col, const typename MaskOf<C>::type *__restrict__ masks,
+    const T *__restrict__ val, const T *__restrict__ x, T *__restrict__ y)
+{
+    using Cfg = StreamCfg<T, R, C, NVG>;
+    constexpr int U = Cfg::U, BT = Cfg::BT;
+    __shared__ v4u s_val[Cfg::VVEC];
+    __shared__ v4u s_mask[Cfg::MVEC];
+    __shared__ v4u s_col[Cfg::CVEC];
+    __shared__ v4u s_bp[Cfg::PVEC];
+    __shared__ T s_x[BT * C];
+    __shared__ int s_boff[BT];
+    __shared__ int s_wsum[kWG / kWave];
+
+    const int th = threadIdx.x;
+    const int lane = lane_id();
+    const int wv = th / kWave;
+    const int64_t g = remap ? xcd_remap(blockIdx.x, nwg) : (int64_t)blockIdx.x;
+    const int64_t t_begin = g * tiles_per_wg;
+    const int64_t t_end = min(t_begin + tiles_per_wg, ntiles);
+    const Buf xbuf = make_buf(x, ncols * (int64_t)sizeof(T));
+
+    int p0 = tile_p[t_begin], p1 = tile_p[t_begin + 1];
+    int b0 = tile_b[t_begin], b1 = tile_b[t_begin + 1];
+    int v0 = tile_v[t_begin], v1 = tile_v[t_begin + 1];
+    TileStage<T, R, C, NVG> st;
+    st.issue(p0, p1, b0, b1, v0, v1, val, masks, blk_col, blk_ptr);
+
+    for (int64_t t = t_begin; t < t_end; ++t) {
+        // next tile's bounds (scalar loads, their own counter)
+        const bool more = t + 1 < t_end;
+        const int64_t tn = more ? t + 1 : t;
+        const int q0 = tile_p[tn], q1 = tile_p[tn + 1];
+        const int c0 = tile_b[tn], c1 = tile_b[tn + 1];
+        const int w0 = tile_v[tn], w1 = tile_v[tn + 1];
+
+        // 1. land the staged tile in LDS
+        __syncthreads();
+        st.rm.commit(s_mask, st.qm);
+        st.rc.commit(s_col, st.qc);
+        st.rp.commit(s_bp, st.qp);
+        st.rv.commit(s_val, st.qv);
+        const int skv = st.qv.skew, skm = st.qm.skew, skc = st.qc.skew, skp = st.qp.skew;
+        __syncthreads();
+        const uint8_t *smb = (const uint8_t *)s_mask + skm;
+        const int *scol = (const int *)((const uint8_t *)s_col + skc);
+        const int *sbp = (const int *)((const uint8_t *)s_bp + skp);
+        const T *sval = (const T *)((const uint8_t *)s_val + skv);
+        const int np = p1 - p0;
+        const int nbt = b1 - b0;
+
+        // 3. single x load per block (thread per block) ...
+        const bool has = th < nbt;
+        const int tb = has ? th : 0;
+        const unsigned un = has ? lds_block_union<R, C>(smb, tb) : 0u;
+        const int col0 = has ? scol[tb] : 0;
+        T xw[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+            xw[k] = buf_load<T>(xbuf, ((un >> k) & 1u) ? (uint32_t)(col0 + k) * (uint32_t)sizeof(T)
+                                                       : kOOB);
+        // ... then the next tile's staging loads, so both are in flight
+        // together and waiting for the gathers does not wait for them.  On the
+        // last tile the current tile is re-requested (cache hits): keeping the
+        // issue unconditional keeps the load counters exact on every path.
+        st.issue(q0, q1, c0, c1, w0, w1, val, masks, blk_col, blk_ptr);
+
+        // 2. block value offsets (workgroup exclusive scan of block popcounts)
+        int cnt = 0;
+        if (has) {
+            unsigned mm;
+            int pp;
+            lds_block_masks<R, C>(smb, tb, 0, mm, pp, cnt);
+        }
+        const int incl = wave_incl_scan(cnt);
+        if (lane == kWave - 1) s_wsum[wv] = incl;
+        if (has) {
+#pragma unroll
+            for (int k = 0; k < C; ++k) s_x[tb * C + k] = xw[k];
+        }
+        __syncthreads();
+        {
+            int before = 0;
+#pragma unroll
+            for (int w2 = 0; w2 < kWG / kWave; ++w2) before += w2 < wv ? s_wsum[w2] : 0;
+            if (has) s_boff[tb] = before + incl - cnt;
+        }
+        __syncthreads();
+
+        // 4. rows: thread = (panel, sub-lane, row); S sub-lanes per row with
+        //    np*R*S <= 256 and S*R <= 64 (the butterfly stays in a wavefront)
+        int lgS = 0;
+        if ((R & (R - 1)) == 0)
+            while (np * R * (2 << lgS) <= kWG && R * (2 << lgS) <= kWave) ++lgS;
+        const int S = 1 << lgS;
+        const int lps = S * R;
+        const int pl = th / lps, sub = (th / R) & (S - 1), i = th % R;
+        const bool live = pl < np;
+        const int bs = live ? sbp[pl] - b0 : 0;
+        const int be = live ? sbp[pl + 1] - b0 : 0;
+        T acc = T(0);
+        for (int b = bs + sub; b < be; b += U * S) {
+            unsigned m[U];
+            int j[U], tt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = b + u * S < be;
+                tt[u] = ok ? b + u * S : b;
+                int pre, tot;
+                lds_block_masks<R, C>(smb, tt[u], i, m[u], pre, tot);
+                m[u] = ok ? m[u] : 0u;
+                j[u] = s_boff[tt[u]] + pre;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    const bool on = (m[u] >> k) & 1u;
+                    const T v = sval[on ? j[u] : 0];
+                    const T xv = s_x[tt[u] * C + k];
+                    const T r = fma(v, xv, acc);
+                    acc = on ? r : acc;
+                    j[u] += on ? 1 : 0;
+                }
+            }
+        }
+        // 5. sub-lanes of a row are R apart inside one wavefront
+        for (int d = R; d < lps; d <<= 1) acc += __shfl_xor(acc, d);
+        if (live && sub == 0) {
+            const int64_t row = (int64_t)(p0 + pl) * R + i;
+            if (row < nrows) y[row] = acc;
+        }
+        p0 = q0; p1 = q1; b0 = c0; b1 = c1; v0 = w0; v1 = w1;
+    }
+}
+
+// ---------------------------------------------------------------- schedule
+
+// Greedy tiles inside each group of ppw consecutive panels: a panel starts a
+// new tile when adding it would pass vt values or bt blocks.  One thread per
+// group; pass 0 counts the tiles of each group, pass 1 writes them.  A panel
+// larger than a whole tile sets *bad.
+__global__ void k_tile_groups(int pass, int64_t npanels, int ppw, int vt, int bt,
+                              const int32_t *bp, const int32_t *pv, int64_t *count,
+                              const int64_t *first, int32_t *tp, int32_t *tb, int32_t *tv,
+                              int *bad, int *maxvals) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ng = (npanels + ppw - 1) / ppw;
+    if (g >= ng) return;
+    const int64_t pa = g * ppw, pz = min(pa + ppw, npanels);
+    int64_t n = 0, o = pass ? first[g] : 0;
+    int64_t start = pa;
+    for (int64_t p = pa; p < pz; ++p) {
+        if (pv[p + 1] - pv[p] > vt || bp[p + 1] - bp[p] > bt) atomicOr(bad, 1);
+        const bool cut = p > start && (pv[p + 1] - pv[start] > vt || bp[p + 1] - bp[start] > bt);
+        if (p == pa || cut) {
+            if (pass) {
+                tp[o + n] = (int32_t)p;
+                tb[o + n] = bp[p];
+                tv[o + n] = pv[p];
+            }
+            if (p > pa) atomicMax(maxvals, pv[p] - pv[start]);
+            ++n;
+            start = p;
+        }
+    }
+    atomicMax(maxvals, pv[pz] - pv[start]);
+    if (!pass) count[g] = n;
+}
+
+__global__ void k_tile_sentinel(int64_t npanels, int64_t ntiles, const int32_t *bp,
+                                const int32_t *pv, int32_t *tp, int32_t *tb, int32_t *tv) {
+    tp[ntiles] = (int32_t)npanels;
+    tb[ntiles] = bp[npanels];
+    tv[ntiles] = pv[npanels];
+}
+
+int build_staged_schedule(spc5_matrix *A, int ppw_req) {
+    if (A->tile_p) { (void)hipFree(A->tile_p); A->tile_p = nullptr; }
+    if (A->tile_b) { (void)hipFree(A->tile_b); A->tile_b = nullptr; }
+    if (A->tile_v) { (void)hipFree(A->tile_v); A->tile_v = nullptr; }
+    A->ntiles_staged = 0;
+    A->staged_ok = true;
+    int vt, bt, ppw;
+    staged_caps(A, &vt, &bt, &ppw);
+    if (ppw_req > 0) ppw = std::min(ppw, ppw_req);
+    A->sppt = ppw;
+    if (A->npanels == 0) return SPC5_OK;
+    hipStream_t s = nullptr;
+    hipError_t e;
+    int64_t *count = nullptr, *first = nullptr, *scratch = nullptr;
+    int *bad = nullptr;
+    int status = SPC5_OK;
+    A->max_tile_values = 0;
+    auto cleanup = [&]() {
+        if (count) (void)hipFree(count);
+        if (first) (void)hipFree(first);
+        if (scratch) (void)hipFree(scratch);
+        if (bad) (void)hipFree(bad);
+    };
+    const int64_t np = A->npanels;
+    const int64_t ng = (np + ppw - 1) / ppw;
+    const unsigned grid = (unsigned)((ng + 255) / 256);
+    if ((e = hipMalloc((void **)&count, (size_t)ng * 8)) != hipSuccess ||
+        (e = hipMalloc((void **)&first, (size_t)(ng + 1) * 8)) != hipSuccess ||
+        (e = hipMalloc((void **)&bad, 8)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "allocating the tile schedule");
+    }
+    if ((e = zero_fill(bad, 2, 4, s)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "clearing the schedule flag");
+    }
+    hipLaunchKernelGGL(k_tile_groups, dim3(grid), dim3(256), 0, s, 0, np, ppw, vt, bt,
+                       A->blk_ptr, A->panel_val, count, (const int64_t *)nullptr,
+                       (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, bad, bad + 1);
+    if ((e = hipGetLastError()) != hipSuccess ||
+        (e = excl_scan_i64(count, ng, first, s, &scratch)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "counting tiles");
+    }
+    int64_t ntiles = 0;
+    int hbad[2] = {0, 0};
+    if ((e = hipMemcpy(&ntiles, first + ng, 8, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(hbad, bad, 8, hipMemcpyDeviceToHost)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "reading the tile count");
+    }
+    A->staged_ok = hbad[0] == 0;
+    A->max_tile_values = hbad[1];
+    const size_t nt1 = (size_t)ntiles + 1;
+    if ((e = hipMalloc((void **)&A->tile_p, nt1 * 4 + kPad)) != hipSuccess ||
+        (e = hipMalloc((void **)&A->tile_b, nt1 * 4 + kPad)) != hipSuccess ||
+        (e = hipMalloc((void **)&A->tile_v, nt1 * 4 + kPad)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "allocating the tile schedule");
+    }
+    hipLaunchKernelGGL(k_tile_groups, dim3(grid), dim3(256), 0, s, 1, np, ppw, vt, bt,
+                       A->blk_ptr, A->panel_val, (int64_t *)nullptr, first, A->tile_p,
+                       A->tile_b, A->tile_v, bad, bad + 1);
+    hipLaunchKernelGGL(k_tile_sentinel, dim3(1), dim3(1), 0, s, np, ntiles, A->blk_ptr,
+                       A->panel_val, A->tile_p, A->tile_b, A->tile_v);
+    if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
+        status = hip_fail(e, "filling the tile schedule");
+    A->ntiles_staged = ntiles;
+    cleanup();
+    return status;
+}
+
+// ---------------------------------------------------------------- launch
+
+template <typename T, int R, int C, int NVG>
+static hipError_t launch_stream_g(const spc5_matrix *A, const T *val, const T *x, T *y,
+                                  hipStream_t s, int remap) {
+    const int64_t nt = A->ntiles_staged;
+    if (nt == 0) return hipSuccess;
+    // consecutive tiles per workgroup (the next one is prefetched)
+    static int tpw = -1;
+    if (tpw < 0) {
+        const char *e = getenv("SPC5_TILES_PER_WG");
+        tpw = e ? std::max(1, atoi(e)) : 4;
+    }
+    const int64_t nwg = (nt + tpw - 1) / tpw;
+    hipLaunchKernelGGL((k_spmv_stream<T, R, C, NVG>), dim3((unsigned)nwg), dim3(kWG), 0, s, A->nrows,
+                       A->ncols, nt, tpw, nwg, remap, A->tile_p, A->tile_b, A->tile_v, A->blk_ptr,
+                       A->blk_col, (const typename MaskOf<C>::type *)A->masks, val, x, y);
+    return hipGetLastError();
+}
+
+// LDS value buffer sized to the largest tile of the matrix: 4, 8 or 16 KiB.
+template <typename T, int R, int C>
+static hipError_t launch_stream(const spc5_matrix *A, const T *val, const T *x, T *y,
+                                hipStream_t s, int remap) {
+    const int64_t need = (int64_t)A->max_tile_values * (int64_t)sizeof(T) + 16;
+    if (need <= 4096) return launch_stream_g<T, R, C, 1>(A, val, x, y, s, remap);
+    if (need <= 8192) return launch_stream_g<T, R, C, 2>(A, val, x, y, s, remap);
+    return launch_stream_g<T, R, C, 4>(A, val, x, y, s, remap);
+}
+
+template <typename T>
+static hipError_t staged_dispatch(const spc5_matrix *A, const void *val, const void *x, void *y,
+                                  hipStream_t s, int remap) {
+#define SPC5_CASE(RR, CC)                                                                    \
+    case RR * 100 + CC:                                                                     \
+        return launch_stream<T, RR, CC>(A, (const T *)val, (const T *)x, (T *)y, s, remap);
+#define SPC5_ROW(RR) SPC5_CASE(RR, 4) SPC5_CASE(RR, 8) SPC5_CASE(RR, 16)
+    switch (A->r * 100 + (A->c <= 4 ? 4 : (A->c <= 8 ? 8 : 16))) {
+        SPC5_ROW(1) SPC5_ROW(2) SPC5_ROW(3) SPC5_ROW(4)
+        SPC5_ROW(5) SPC5_ROW(6) SPC5_ROW(7) SPC5_ROW(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef SPC5_ROW
+#undef SPC5_CASE
+}
+
+hipError_t launch_spmv_staged(const spc5_matrix *A, const void *val, const void *x, void *y,
+                              hipStream_t s, int remap) {
+    if (!A->staged_ok) return hipErrorInvalidValue;
+    return A->dtype == SPC5_F64 ? staged_dispatch<double>(A, val, x, y, s, remap)
+                                : staged_dispatch<float>(A, val, x, y, s, remap);
+}
+
+}  // namespace spc5

@@ -33,6 +33,33 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n) {
     return xcd * q + (xcd < rem ? xcd : rem) + idx;
 }
 
+// Raw buffer loads.  A load whose byte offset lies at or beyond the
+// descriptor's record count returns 0 and moves no data, which gives
+// predicated gathers without branches: the lanes whose mask bit is clear pass
+// kOOB.  Record counts are kept below 2^31 so kOOB is always out of range.
+constexpr uint32_t kOOB = 0x80000000u;
+constexpr int64_t kMaxBufBytes = 0x7FFFFFF0;
+
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+};
+
+__device__ __forceinline__ Buf make_buf(const void *p, int64_t bytes) {
+    Buf b;
+    const int nrec = (int)(bytes < kMaxBufBytes ? bytes : kMaxBufBytes);
+    // word 3: 32-bit data format, raw (unswizzled) addressing
+    b.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, nrec, 0x00020000);
+    return b;
+}
+
+template <typename T> __device__ __forceinline__ T buf_load(const Buf &b, uint32_t off);
+template <> __device__ __forceinline__ double buf_load<double>(const Buf &b, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)off, 0, 0));
+}
+template <> __device__ __forceinline__ float buf_load<float>(const Buf &b, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)off, 0, 0));
+}
+
 template <int C> struct MaskOf { using type = uint8_t; };
 template <> struct MaskOf<16> { using type = uint16_t; };
 

@@ -16,6 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libspc5.so")
 
 SPC5_F64, SPC5_F32 = 0, 1
+KERNEL_AUTO, KERNEL_ROWS, KERNEL_SWEEP, KERNEL_STAGED = 0, 1, 2, 3
 STATUS = {0: "SPC5_OK", -1: "SPC5_EINVAL", -2: "SPC5_EBADCSR", -3: "SPC5_ENOMEM",
           -4: "SPC5_EDEVICE", -5: "SPC5_EUNSUPPORTED"}
 
@@ -40,7 +41,8 @@ class spc5_info(ctypes.Structure):
                 ("nblocks", ctypes.c_int64), ("npanels", ctypes.c_int64),
                 ("r", ctypes.c_int32), ("c", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("mask_bytes", ctypes.c_int32), ("panels_per_tile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("ntiles", ctypes.c_int64),
+                ("kernel", ctypes.c_int32), ("ntiles", ctypes.c_int64),
+                ("max_panel_blocks", ctypes.c_int64),
                 ("fill", ctypes.c_double), ("spmv_bytes", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64)]
 
@@ -62,7 +64,7 @@ def lib():
         L.spc5_free.restype = None
         L.spc5_get_info.argtypes = [P, ctypes.POINTER(spc5_info)]
         L.spc5_export.argtypes = [P, P, P, P, P]
-        L.spc5_set_schedule.argtypes = [P, I]
+        L.spc5_set_schedule.argtypes = [P, I, I]
         L.spc5_spmv.argtypes = [P, P, P, P]
         L.spc5_spmv_values.argtypes = [P, P, P, P, P]
         L.spc5_spmv_transpose.argtypes = [P, P, P, P]
@@ -181,9 +183,18 @@ class Spc5Matrix:
         except Exception:
             pass
 
-    def set_schedule(self, panels_per_tile: int):
-        _check(lib().spc5_set_schedule(self._h, panels_per_tile))
+    def set_schedule(self, kernel: str = "auto", panels_per_tile: int = 0):
+        """kernel: 'auto', 'staged', 'rows' or 'sweep'; panels_per_tile: tile
+        width of the staged and sweep kernels (0 = default)."""
+        code = {"auto": KERNEL_AUTO, "rows": KERNEL_ROWS, "sweep": KERNEL_SWEEP,
+                "staged": KERNEL_STAGED}[kernel]
+        _check(lib().spc5_set_schedule(self._h, code, panels_per_tile))
         self.info = self._info()
+
+    @property
+    def kernel(self) -> str:
+        return {KERNEL_ROWS: "rows", KERNEL_SWEEP: "sweep",
+                KERNEL_STAGED: "staged"}[self.info.kernel]
 
     def export(self):
         """Host copies of (blk_ptr int64, blk_col int32, masks uint8/16, values)."""
