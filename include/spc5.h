@@ -174,17 +174,39 @@ int spc5_spmm(const spc5_matrix *A, int nrhs, const void *X, void *Y, void *stre
 
 /* ---------------------------------------------------------------- batches */
 
-/* Group matrices of one dtype so that Y_m = A_m X_m for all m runs as one
- * launch (tiles of every matrix in a single grid).  The batch keeps pointers
- * to the handles (which must outlive it) and owns its own device tables.
+/* Group matrices of one dtype so that Y_m = A_m X_m for every m runs as ONE
+ * persistent launch: workgroups take (matrix, tile) work items from a device
+ * queue until it is empty, so matrices of very different sizes share the GPU
+ * evenly.  Shapes must come from the batched kernel's set: beta(1,4),
+ * beta(1,8), beta(1,16), beta(2,4), beta(2,8), beta(4,4), beta(4,8),
+ * beta(8,8) (else SPC5_EUNSUPPORTED).  The batch keeps pointers to the
+ * handles, which must outlive it, and owns its own device tables.
  * Synchronous. */
 int spc5_batch_create(int nmat, spc5_matrix *const *mats, spc5_batch **out);
 void spc5_batch_free(spc5_batch *B);
 
-/* X[m], Y[m]: host arrays of nmat device pointers, laid out as in spc5_spmm
- * with the same nrhs for every matrix. */
+/* Bind the operands: X[m], Y[m] are host arrays of nmat device pointers,
+ * laid out as in spc5_spmm, with the same nrhs (1..64) for every matrix.  The
+ * pointer table and the work list are uploaded here (synchronous), so that
+ * spc5_batch_run itself issues only kernels. */
+int spc5_batch_set_operands(spc5_batch *B, int nrhs, const void *const *X,
+                            void *const *Y);
+
+/* Y_m = A_m X_m for all m with the bound operands: one queue-reset kernel
+ * and one persistent launch on `stream`, no allocation and no host-device
+ * copy, so the call can be recorded in a HIP graph and replayed. */
+int spc5_batch_run(const spc5_batch *B, void *stream);
+
+/* spc5_batch_set_operands followed by spc5_batch_run. */
 int spc5_batch_spmm(spc5_batch *B, int nrhs, const void *const *X,
                     void *const *Y, void *stream);
+
+/* Cost model input for choosing beta(r,c): for each candidate q, the number of
+ * blocks of the CSR matrix in beta(r[q], c[q]) (counted on the device; the
+ * matrix is not converted).  Arguments as in csr_to_spc5 (values are not
+ * needed); nblocks: host int64[ncand].  Synchronous. */
+int spc5_plan(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *colidx,
+              int ncand, const int *r, const int *c, int64_t *nblocks);
 
 /* ---------------------------------------------------------------- CSR */
 

@@ -72,7 +72,7 @@ static bool alloc_fail_hook() {
 }
 
 // Host-side CSR validation, parallel over row ranges.
-static int validate_csr(int64_t nrows, int64_t ncols, const int64_t *rowptr,
+int validate_csr(int64_t nrows, int64_t ncols, const int64_t *rowptr,
                         const int32_t *colidx, const void *values, int64_t *nnz_out) {
     if (!rowptr) return fail(SPC5_EINVAL, "rowptr is NULL");
     if (rowptr[0] != 0) return fail(SPC5_EBADCSR, "rowptr[0] = %lld, expected 0",

@@ -207,6 +207,32 @@ static hipError_t launch_block_any(bool fill, spc5_matrix *A, const int64_t *row
                : launch_block<float, uint16_t>(fill, A, rowptr, colidx, vin, count, bptr, s);
 }
 
+int count_blocks_device(const int64_t *d_rowptr, const int32_t *d_colidx, int64_t nrows, int r,
+                        int c, int64_t *nblocks) {
+    spc5_matrix tmp;
+    tmp.nrows = nrows;
+    tmp.npanels = (nrows + r - 1) / r;
+    tmp.r = r;
+    tmp.c = c;
+    tmp.mask_bytes = c <= 8 ? 1 : 2;
+    hipStream_t s = nullptr;
+    hipError_t e;
+    int64_t *count = nullptr, *bptr64 = nullptr, *scratch = nullptr;
+    const size_t np1 = (size_t)tmp.npanels + 1;
+    int st = SPC5_OK;
+    if ((e = hipMalloc((void **)&count, np1 * 8)) != hipSuccess ||
+        (e = hipMalloc((void **)&bptr64, np1 * 8)) != hipSuccess ||
+        (e = launch_block_any(false, &tmp, d_rowptr, d_colidx, nullptr, count, nullptr, s)) !=
+            hipSuccess ||
+        (e = excl_scan_i64(count, tmp.npanels, bptr64, s, &scratch)) != hipSuccess ||
+        (e = hipMemcpy(nblocks, bptr64 + tmp.npanels, 8, hipMemcpyDeviceToHost)) != hipSuccess)
+        st = hip_fail(e, "counting blocks");
+    if (count) (void)hipFree(count);
+    if (bptr64) (void)hipFree(bptr64);
+    if (scratch) (void)hipFree(scratch);
+    return st;
+}
+
 int convert_on_device(spc5_matrix *A, const int64_t *d_rowptr, const int32_t *d_colidx,
                       const void *d_values) {
     hipStream_t s = nullptr;

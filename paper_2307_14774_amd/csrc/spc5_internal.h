@@ -53,6 +53,10 @@ int hip_fail(hipError_t e, const char *what);
 // Default wavefront tile width (in panels) for a mean number of block rows
 // per panel.
 int default_ppt(double blockrows_per_panel);
+// Host-side CSR checks (rowptr monotone from 0, columns sorted, unique and in
+// range, nnz < 2^31); *nnz_out receives rowptr[nrows].
+int validate_csr(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *colidx,
+                 const void *values, int64_t *nnz_out);
 // Forward kernel picked from the panel statistics of A.
 int auto_kernel(const spc5_matrix *A);
 

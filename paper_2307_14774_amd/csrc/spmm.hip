@@ -4,11 +4,9 @@
 // anchor+k of X for each set mask bit, so the matrix is streamed once per
 // chunk of K right-hand sides instead of once per vector.
 #include "spc5_internal.h"
-#include "tile.h"
+#include "spmm_tile.h"
 
 namespace spc5 {
-
-constexpr int kSpmmTile = 1024;   // LDS row accumulators per wavefront (ppt*R*K)
 
 template <typename T, int R, int C, int K>
 __global__ __launch_bounds__(kWave) void k_spmm(
@@ -17,61 +15,9 @@ __global__ __launch_bounds__(kWave) void k_spmm(
     const typename MaskOf<C>::type *__restrict__ masks, const T *__restrict__ val,
     const int32_t *__restrict__ panel_val, const T *__restrict__ X, T *__restrict__ Y, int ld)
 {
-    constexpr int BPS = kWave / R;
-    constexpr int LANES = BPS * R;
     __shared__ T ytile[kSpmmTile];
-    const int lane = lane_id();
-    const TileCtx t = tile_begin(xcd_remap(blockIdx.x, ntiles), ppt, npanels, blk_ptr);
-    for (int q = lane; q < t.np * R * K; q += kWave) ytile[q] = T(0);
-    __syncthreads();
-    const int i = lane % R;
-    const int bl = lane / R;
-    int vbase = panel_val[t.p0];
-    for (int bs = t.b0; bs < t.b1; bs += BPS) {
-        const int b = bs + bl;
-        const bool act = (lane < LANES) && (b < t.b1);
-        const unsigned m = act ? (unsigned)masks[(int64_t)b * R + i] : 0u;
-        const int col0 = act ? blk_col[b] : 0;
-        const int cnt = __popc(m);
-        const int incl = wave_incl_scan(cnt);
-        int j = vbase + incl - cnt;
-        vbase += __shfl(incl, kWave - 1);
-        const int pid = tile_panel_of(b, t.pe);
-        T acc[K];
-#pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] = T(0);
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            if ((m >> k) & 1u) {
-                const T v = val[j];
-                const T *xr = X + (int64_t)(col0 + k) * ld;
-#pragma unroll
-                for (int q = 0; q < K; ++q) acc[q] = fma(v, xr[q], acc[q]);
-                ++j;
-            }
-        }
-#pragma unroll
-        for (int d = R; d < kWave; d <<= 1) {
-            const int op = __shfl_up(pid, d);
-            const bool take = lane >= d && op == pid;
-#pragma unroll
-            for (int q = 0; q < K; ++q) {
-                const T o = __shfl_up(acc[q], d);
-                if (take) acc[q] += o;
-            }
-        }
-        const int pn = __shfl_down(pid, R);
-        const int bn = __shfl_down(b, R);
-        const bool tail = act && (lane + R >= LANES || bn >= t.b1 || pn != pid);
-        if (tail) {
-#pragma unroll
-            for (int q = 0; q < K; ++q) ytile[(pid * R + i) * K + q] += acc[q];
-        }
-    }
-    __syncthreads();
-    const int64_t row0 = t.p0 * R;
-    const int nr = (int)min((int64_t)t.np * R, nrows - row0);
-    for (int q = lane; q < nr * K; q += kWave) Y[(row0 + q / K) * ld + q % K] = ytile[q];
+    spmm_tile<T, R, C, K>(xcd_remap(blockIdx.x, ntiles), ppt, npanels, nrows, blk_ptr, blk_col,
+                          masks, val, panel_val, X, Y, ld, ytile);
 }
 
 template <typename T, int R, int C, int K>
@@ -131,20 +77,3 @@ hipError_t launch_spmm(const spc5_matrix *A, int nrhs, const void *X, void *Y,
 
 }  // namespace spc5
 
-extern "C" {
-
-int spc5_batch_create(int nmat, spc5_matrix *const *mats, spc5_batch **out) {
-    (void)nmat; (void)mats;
-    if (out) *out = nullptr;
-    return spc5::fail(SPC5_EUNSUPPORTED, "batched launch not available yet");
-}
-
-void spc5_batch_free(spc5_batch *B) { (void)B; }
-
-int spc5_batch_spmm(spc5_batch *B, int nrhs, const void *const *X, void *const *Y,
-                    void *stream) {
-    (void)B; (void)nrhs; (void)X; (void)Y; (void)stream;
-    return spc5::fail(SPC5_EUNSUPPORTED, "batched launch not available yet");
-}
-
-}  // extern "C"

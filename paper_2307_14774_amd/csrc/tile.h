@@ -8,6 +8,8 @@
 
 namespace spc5 {
 
+constexpr int kSpmmTile = 1024;   // LDS row accumulators per wavefront (ppt*R*K)
+
 struct TileCtx {
     int64_t p0;   // first panel of the tile
     int np;       // panels in the tile

@@ -25,7 +25,8 @@ EXPORTS = [
     "csr_to_spc5", "spc5_free", "spc5_get_info", "spc5_export", "spc5_set_schedule",
     "spc5_spmv", "spc5_spmv_values", "spc5_spmv_transpose", "spc5_spmv_transpose_values",
     "spc5_values_grad", "spc5_spmm", "spc5_batch_create", "spc5_batch_free",
-    "spc5_batch_spmm", "spc5_csr_create", "spc5_csr_free", "spc5_csr_spmv",
+    "spc5_batch_set_operands", "spc5_batch_run", "spc5_batch_spmm", "spc5_plan",
+    "spc5_csr_create", "spc5_csr_free", "spc5_csr_spmv",
     "spc5_csr_bytes", "spc5_last_error", "spc5_version",
 ]
 
@@ -75,6 +76,9 @@ def lib():
         L.spc5_batch_free.argtypes = [P]
         L.spc5_batch_free.restype = None
         L.spc5_batch_spmm.argtypes = [P, I, P, P, P]
+        L.spc5_batch_set_operands.argtypes = [P, I, P, P]
+        L.spc5_batch_run.argtypes = [P, P]
+        L.spc5_plan.argtypes = [I64, I64, P, P, I, P, P, P]
         L.spc5_csr_create.argtypes = [I64, I64, P, P, P, I, ctypes.POINTER(P)]
         L.spc5_csr_free.argtypes = [P]
         L.spc5_csr_free.restype = None
@@ -319,3 +323,68 @@ def spc5_spmv_transpose(A: Spc5Matrix, ybar, xbar, stream=None):
 
 def spc5_free(A: Spc5Matrix):
     A.free()
+
+
+def plan(rowptr, colidx, ncols: int, candidates):
+    """Block counts of the CSR matrix for each candidate (r, c), counted on the
+    device without converting (spc5_plan)."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    colidx = np.ascontiguousarray(colidx, dtype=np.int32)
+    rs = np.ascontiguousarray([r for r, _ in candidates], dtype=np.int32)
+    cs = np.ascontiguousarray([c for _, c in candidates], dtype=np.int32)
+    out = np.zeros(len(candidates), dtype=np.int64)
+    _check(lib().spc5_plan(rowptr.shape[0] - 1, ncols, _np_ptr(rowptr), _np_ptr(colidx),
+                           len(candidates), _np_ptr(rs), _np_ptr(cs), _np_ptr(out)))
+    return [int(v) for v in out]
+
+
+class Spc5Batch:
+    """Several matrices of one dtype, multiplied in one persistent launch."""
+
+    def __init__(self, mats):
+        self.mats = list(mats)
+        arr = (ctypes.c_void_p * len(self.mats))(*[m.handle for m in self.mats])
+        h = ctypes.c_void_p()
+        _check(lib().spc5_batch_create(len(self.mats), arr, ctypes.byref(h)))
+        self._h = h
+        self._bound = None
+
+    def set_operands(self, Xs, Ys):
+        """Xs[m]: (ncols_m, k) device tensors, Ys[m]: (nrows_m, k); same k."""
+        if len(Xs) != len(self.mats) or len(Ys) != len(self.mats):
+            raise ValueError("one X and one Y per matrix")
+        k = Xs[0].shape[1]
+        xp, yp = [], []
+        for M, X, Y in zip(self.mats, Xs, Ys):
+            inf = M.info
+            if X.dim() != 2 or X.shape[1] != k or Y.dim() != 2 or Y.shape[1] != k:
+                raise ValueError("X and Y must be 2-D with the same number of columns")
+            xp.append(_dev_ptr(X, inf.dtype, inf.ncols * k, "X").value)
+            yp.append(_dev_ptr(Y, inf.dtype, inf.nrows * k, "Y").value)
+        xa = (ctypes.c_void_p * len(xp))(*xp)
+        ya = (ctypes.c_void_p * len(yp))(*yp)
+        _check(lib().spc5_batch_set_operands(self._h, k, xa, ya))
+        self._bound = (list(Xs), list(Ys))   # keep the tensors alive
+
+    def run(self, stream=None):
+        _check(lib().spc5_batch_run(self._h, _stream(stream)))
+
+    def spmm(self, Xs, Ys=None, stream=None):
+        import torch
+        if Ys is None:
+            Ys = [torch.empty((M.info.nrows, X.shape[1]), dtype=M.torch_dtype, device=X.device)
+                  for M, X in zip(self.mats, Xs)]
+        self.set_operands(Xs, Ys)
+        self.run(stream)
+        return Ys
+
+    def free(self):
+        if self._h:
+            lib().spc5_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -190,29 +190,60 @@ def random_sparse(nrows: int, ncols: int, density: float, seed: int = 0,
                    f"rand{nrows}x{ncols}d{density}")
 
 
-def banded_runs(nrows: int, ncols: int, seed: int = 0, max_len: int = 512,
-                zipf_s: float = 1.5, run_frac: float = 0.3) -> Csr:
-    """Power-law row lengths min(Zipf(zipf_s), max_len); about `run_frac` of a
-    row's nonzeros come in runs of 2..16 consecutive columns at uniform starts,
-    the rest are uniform singletons; duplicates are removed and topped up.
-    Values and x U(-1,1)."""
-    rng = np.random.default_rng(seed)
-    lengths = np.minimum(rng.zipf(zipf_s, nrows), min(max_len, ncols)).astype(np.int64)
-    rows_cols = []
-    for i in range(nrows):
-        L = int(lengths[i])
-        want_run = int(round(run_frac * L))
-        cols = set()
-        while want_run > 1 and len(cols) < want_run:
-            rl = int(rng.integers(2, 17))
-            rl = min(rl, want_run - len(cols)) if want_run - len(cols) >= 2 else 2
-            st = int(rng.integers(0, max(ncols - rl + 1, 1)))
-            cols.update(range(st, min(st + rl, ncols)))
-        while len(cols) < L:
-            cols.add(int(rng.integers(0, ncols)))
-        rows_cols.append(np.array(sorted(cols), dtype=np.int32))
-    counts = np.array([len(c) for c in rows_cols], dtype=np.int64)
-    colidx = np.concatenate(rows_cols) if rows_cols else np.zeros(0, np.int32)
-    values = rng.uniform(-1.0, 1.0, colidx.shape[0])
-    x = rng.uniform(-1.0, 1.0, ncols)
-    return _finish(nrows, ncols, counts, colidx, values, x, f"runs{nrows}")
+def runs_matrix(n: int, rng, zipf_s: float = 1.5, cap: int = 512,
+                run_frac: float = 0.3) -> Csr:
+    """Square n x n matrix with power-law row lengths L = min(Zipf(zipf_s), cap)
+    (the literal cap: lengths above it are set to it).  About `run_frac` of a
+    row's nonzeros come in runs of 2..16 consecutive columns at uniform
+    starts, the rest are uniform singletons; duplicates are merged and rows
+    topped up with singletons, so a row may end a few entries above L when a
+    run overshoots.  Values U(-1,1); x U(-1,1).
+
+    Draw order: L, run lengths, run starts, singleton columns, top-ups,
+    values, x."""
+    L = np.minimum(rng.zipf(zipf_s, n), min(cap, n)).astype(np.int64)
+    want_runs = np.round(run_frac * L).astype(np.int64)
+    want_runs[want_runs < 2] = 0
+    nruns = (want_runs + 8) // 9                      # mean run length 9
+    rrow = np.repeat(np.arange(n, dtype=np.int64), nruns)
+    rlen = rng.integers(2, 17, rrow.shape[0])
+    rlen = np.minimum(rlen, n)
+    rstart = (rng.random(rrow.shape[0]) * (n - rlen + 1)).astype(np.int64)
+    # expand runs into (row, col)
+    tot = int(rlen.sum())
+    rid = np.repeat(np.arange(rrow.shape[0]), rlen)
+    within = np.arange(tot) - np.repeat(np.cumsum(rlen) - rlen, rlen)
+    keys = rrow[rid] * n + rstart[rid] + within
+    run_cnt = np.bincount(rrow, weights=rlen, minlength=n).astype(np.int64)
+    nsing = np.maximum(L - run_cnt, 0)
+    srow = np.repeat(np.arange(n, dtype=np.int64), nsing)
+    keys = np.concatenate([keys, srow * n + rng.integers(0, n, srow.shape[0])])
+    keys = np.unique(keys)
+    for _ in range(20):
+        have = np.bincount(keys // n, minlength=n)
+        need = np.maximum(L - have, 0)
+        if need.sum() == 0:
+            break
+        trow = np.repeat(np.arange(n, dtype=np.int64), need)
+        keys = np.unique(np.concatenate([keys, trow * n + rng.integers(0, n, trow.shape[0])]))
+    rows = keys // n
+    counts = np.bincount(rows, minlength=n)
+    values = rng.uniform(-1.0, 1.0, keys.shape[0])
+    x = rng.uniform(-1.0, 1.0, n)
+    return _finish(n, n, counts, (keys % n).astype(np.int32), values, x, f"runs{n}")
+
+
+def batch_of_runs(nmat: int = 256, seed: int = 0, rows_lo: int = 1000,
+                  rows_hi: int = 200_000) -> list:
+    """`nmat` uneven matrices: n = floor(exp(U(ln rows_lo, ln rows_hi))) rows
+    each (log-uniform sizes), built by runs_matrix with one child seed each
+    (numpy SeedSequence(seed).spawn(nmat))."""
+    children = np.random.SeedSequence(seed).spawn(nmat)
+    out = []
+    for m in range(nmat):
+        rng = np.random.default_rng(children[m])
+        n = int(np.floor(np.exp(rng.uniform(np.log(rows_lo), np.log(rows_hi)))))
+        A = runs_matrix(n, rng)
+        A.name = f"batch{m}_n{n}"
+        out.append(A)
+    return out
