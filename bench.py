@@ -10,8 +10,16 @@ matrix already resident in HBM.  The default workload is the 5-point
 Laplacian on a 2048 x 2048 grid in FP64 with beta(4,4).  One JSON line is
 printed: GFLOP/s (2 flops per stored nonzero), the roofline of the forward
 kernel (algorithmic bytes / measured launch time against 8 TB/s), the other
-formats and the plain CSR kernel on the same GPU, and the CPU oracle timed on
-this host as a baseline.
+formats and the plain CSR kernel on the same GPU, the FEM matrix in FP64 and
+FP32, the differentiated product (forward + backward) on the 2^20 Zipf graph,
+the batched SpMM over 256 uneven matrices, and the CPU oracle timed on this
+host as a baseline.
+
+Profiling helpers (host only, no GPU):
+    python bench.py --traffic-from FETCH.csv WRITE.csv
+reads two rocprofv3 --pmc counter files (FETCH_SIZE, then WRITE_SIZE) of a
+`--calibration-copy` run and writes the HBM traffic per launch of the forward
+kernel, scaled by what the same counters read for a plain copy of known size.
 """
 from __future__ import annotations
 
@@ -27,8 +35,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SpMV GFLOP/s + achieved HBM GB/s (% peak), SPC5 vs CSR, fwd+bwd, FP64/FP32"
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2307_14774_amd/csrc/spmv.hip", "paper_2307_14774_amd/csrc/wave.h",
-                  "paper_2307_14774_amd/csrc/tile.h"]
+KERNEL_SOURCES = ["paper_2307_14774_amd/csrc/staged.hip", "paper_2307_14774_amd/csrc/spmv.hip",
+                  "paper_2307_14774_amd/csrc/wave.h", "paper_2307_14774_amd/csrc/tile.h"]
+FWD_KERNEL = "k_spmv_stream"
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_spc5_fwd.json")
+COPY_ELEMS = 1 << 27          # calibration copy: 1 GiB read + 1 GiB written (float64)
 
 
 def kernel_sha() -> str:
@@ -43,15 +54,22 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+WORKLOADS = {   # name -> (tag, beta(r,c) of the timed product)
+    "laplacian": ("laplacian2d_2048 fp64", (4, 4)),
+    "fem": ("fem3d_96x3 fp64", (4, 4)),
+    "random": ("random10k fp64", (1, 8)),
+}
+
+
 def make_workload(name):
     from paper_2307_14774_amd import workloads as W
-    if name == "laplacian":
-        return W.laplacian_2d(2048, seed=0), (4, 4), "laplacian2d_2048 fp64"
-    if name == "fem":
-        return W.fem_3d(96, seed=0), (4, 4), "fem3d_96x3 fp64"
-    if name == "random":
-        return W.random_uniform(10_000, 10, seed=0), (1, 8), "random10k fp64"
-    raise SystemExit(f"unknown workload {name}")
+    if name not in WORKLOADS:
+        raise SystemExit(f"unknown workload {name}")
+    tag, rc = WORKLOADS[name]
+    A = {"laplacian": lambda: W.laplacian_2d(2048, seed=0),
+         "fem": lambda: W.fem_3d(96, seed=0),
+         "random": lambda: W.random_uniform(10_000, 10, seed=0)}[name]()
+    return A, rc, tag
 
 
 def time_launches(fn, steps, warmup, flush=None):
@@ -77,16 +95,75 @@ def time_launches(fn, steps, warmup, flush=None):
 
 
 def traffic_from_profiles(workload_tag):
-    p = os.path.join(ROOT, "profiles", "traffic_spc5_fwd.json")
-    if not os.path.exists(p):
+    """HBM bytes per launch of the forward kernel from the committed counter
+    summary, or None when it is missing, for another workload, or was taken
+    on kernel sources that have changed since."""
+    if not os.path.exists(TRAFFIC_JSON):
         return None
     try:
-        d = json.load(open(p))
-    except Exception:
+        with open(TRAFFIC_JSON) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
         return None
     if d.get("kernel_sha") != kernel_sha() or d.get("workload") != workload_tag:
         return None
     return d.get("bytes_per_launch")
+
+
+def _counter_means(path, counter):
+    """Mean Counter_Value per dispatch, keyed by kernel name, of one rocprofv3
+    counter-collection CSV (values of one dispatch are summed first)."""
+    import csv
+    per_dispatch = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] != counter:
+                continue
+            key = (row["Dispatch_Id"], row["Kernel_Name"])
+            per_dispatch[key] = per_dispatch.get(key, 0.0) + float(row["Counter_Value"])
+    sums = {}
+    for (_, name), v in per_dispatch.items():
+        n, t = sums.get(name, (0, 0.0))
+        sums[name] = (n + 1, t + v)
+    return {name: (t / n, n) for name, (n, t) in sums.items()}
+
+
+def traffic_write(fetch_csv, write_csv, workload):
+    """Scale the forward kernel's FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+    by what the same counters read for the calibration copy (COPY_ELEMS
+    float64 read and written once) and store bytes per launch."""
+    tag, rc = WORKLOADS[workload]
+    tag = tag + f" beta({rc[0]},{rc[1]})"
+    fetch = _counter_means(fetch_csv, "FETCH_SIZE")
+    write = _counter_means(write_csv, "WRITE_SIZE")
+
+    def pick(table, needle):
+        hits = [(k, v) for k, v in table.items() if needle in k]
+        if len(hits) != 1:
+            raise SystemExit(f"expected one kernel matching {needle!r}, found "
+                             f"{[k[:80] for k, _ in hits]}")
+        return hits[0]
+
+    copy_bytes = COPY_ELEMS * 8
+    kc, (fc, _) = pick(fetch, "neg_kernel")
+    _, (wc, _) = pick(write, "neg_kernel")
+    fetch_factor = copy_bytes / (fc * 1024.0)
+    write_factor = copy_bytes / (wc * 1024.0)
+    kf, (fk, nf) = pick(fetch, FWD_KERNEL)
+    _, (wk, nw) = pick(write, FWD_KERNEL)
+    fetch_b = fk * 1024.0 * fetch_factor
+    write_b = wk * 1024.0 * write_factor
+    out = {"kernel": kf, "kernel_sha": kernel_sha(), "workload": tag,
+           "fetch_kib_per_dispatch": round(fk, 3), "write_kib_per_dispatch": round(wk, 3),
+           "dispatches": [nf, nw], "calibration_kernel": kc,
+           "calibration_bytes_each_way": copy_bytes,
+           "fetch_factor": round(fetch_factor, 4), "write_factor": round(write_factor, 4),
+           "fetch_bytes": int(fetch_b), "write_bytes": int(write_b),
+           "bytes_per_launch": int(fetch_b + write_b)}
+    os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def cpu_baseline(A, rc, budget_s=10.0):
@@ -153,6 +230,173 @@ def fem_extras(dev):
     return res
 
 
+def _avg_us(ms):
+    import numpy as np
+    return float(np.mean(ms)) * 1e3
+
+
+def backward_extras(dev):
+    """Differentiated product y = A(theta) x in FP32 on the 2^20-row graph with
+    Zipf(1.2) column popularity (16.8 M nonzeros): forward, transpose
+    scatter xbar = A^T ybar and packed values gradient, each timed per launch,
+    plus one autograd forward+backward; compared with plain FP64 CSR SpMV
+    on the same matrix.  Parity: transpose against the FP64 oracle on the
+    FP32 data (rel L2), values gradient bit-exact against the oracle's exact
+    products rounded to FP32."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2307_14774_amd import autotune, spc5
+    from paper_2307_14774_amd import workloads as W
+    from paper_2307_14774_amd.autograd import spc5_matvec
+    log("generating the Zipf graph")
+    G = W.zipf_graph(1 << 20, seed=0)
+    (r, c), _ = autotune.choose_shape(G, "float32")
+    log(f"graph beta({r},{c}) fp32")
+    M = spc5.Spc5Matrix.from_csr(G.rowptr, G.colidx, G.values, G.ncols, r, c, "float32")
+    nb = M.info.spmv_bytes
+    rng = np.random.default_rng(0)
+    theta_h = rng.uniform(-1, 1, G.nnz).astype(np.float32)
+    x_h = G.x.astype(np.float32)
+    w_h = rng.standard_normal(G.nrows).astype(np.float32)
+    theta = torch.from_numpy(theta_h).to(dev)
+    x = torch.from_numpy(x_h).to(dev)
+    ybar = torch.from_numpy(w_h).to(dev)
+    y = torch.empty(G.nrows, dtype=torch.float32, device=dev)
+    xbar = torch.empty(G.ncols, dtype=torch.float32, device=dev)
+    vbar = torch.empty(G.nnz, dtype=torch.float32, device=dev)
+    res = {"nrows": G.nrows, "nnz": G.nnz, "beta": [r, c], "fill": round(M.info.fill, 4),
+           "dtype": "f32"}
+    for name, fn in (("forward", lambda: M.spmv_values(theta, x, y)),
+                     ("transpose", lambda: M.transpose(ybar, xbar, values=theta)),
+                     ("values_grad", lambda: M.values_grad(ybar, x, vbar))):
+        _, ms = time_launches(fn, 30, 5)
+        us = _avg_us(ms)
+        res[name] = {"launch_us": round(us, 2), "gbs": round(nb / us / 1e3, 1),
+                     "frac_hbm": round(nb / us / 1e3 / PEAK_HBM_GBS, 4)}
+    res["fwd_bwd_us"] = round(sum(res[k]["launch_us"]
+                                  for k in ("forward", "transpose", "values_grad")), 2)
+    # one full autograd step, wall clock
+    th = theta.clone().requires_grad_(True)
+    xx = x.clone().requires_grad_(True)
+
+    def step():
+        th.grad = None
+        xx.grad = None
+        (spc5_matvec(M, th, xx) * ybar).sum().backward()
+    _, ms = time_launches(step, 10, 3)
+    res["autograd_step_us"] = round(_avg_us(ms), 1)
+    # parity
+    O = oracle.csr_to_spc5(G.rowptr, G.colidx, theta_h.astype(np.float64), G.ncols, r, c)
+    M.transpose(ybar, xbar, values=theta)
+    M.values_grad(ybar, x, vbar)
+    # theta is in packed order: go back to CSR order for the CSR oracle
+    rp, ci, vals = oracle.spc5_to_csr(O)
+    xt_ref = oracle.csr_spmv_t(rp, ci, vals, w_h.astype(np.float64), G.ncols)
+    res["transpose_rel_l2_vs_fp64_oracle"] = oracle.rel_l2(xbar.cpu().numpy(), xt_ref)
+    vg_ref = oracle.spc5_values_grad(O, w_h.astype(np.float64), x_h.astype(np.float64))
+    res["values_grad_bit_exact"] = bool(np.array_equal(vbar.cpu().numpy(),
+                                                       vg_ref.astype(np.float32)))
+    # plain FP64 CSR SpMV on the same matrix
+    C = spc5.CsrMatrix(G.rowptr, G.colidx, G.values, G.ncols)
+    x64 = torch.from_numpy(G.x).to(dev)
+    y64 = torch.empty(G.nrows, dtype=torch.float64, device=dev)
+    _, ms = time_launches(lambda: C.spmv(x64, y64), 30, 5)
+    res["csr_fp64_forward_us"] = round(_avg_us(ms), 2)
+    res["speedup_fwd_vs_csr_fp64"] = round(res["csr_fp64_forward_us"]
+                                           / res["forward"]["launch_us"], 3)
+    res["fwd_bwd_vs_3x_csr_fp64"] = round(3 * res["csr_fp64_forward_us"] / res["fwd_bwd_us"], 3)
+    C.free()
+    M.free()
+    return res
+
+
+def batch_extras(dev, nmat=256, ks=(1, 4, 16)):
+    """NEXT-3 workload: `nmat` uneven matrices (log-uniform 1k..200k rows,
+    Zipf(1.5) row lengths capped at 512, 30% of nonzeros in runs), beta(r,c)
+    per matrix from the byte-model autotuner, k right-hand sides, all in one
+    persistent launch; against plain FP64 single SpMVs (CSR kernel and
+    SPC5 FP64 at the same shapes), one launch per matrix and vector."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2307_14774_amd import autotune, spc5
+    from paper_2307_14774_amd import workloads as W
+    log(f"generating {nmat} batch matrices")
+    mats = W.batch_of_runs(nmat, seed=0)
+    nnz = sum(A.nnz for A in mats)
+    res = {"nmat": nmat, "nnz": nnz, "rows": sum(A.nrows for A in mats)}
+    # plain FP64 single SpMVs: one CSR launch per matrix and vector
+    log("batch: plain FP64 CSR launches")
+    csrs = [spc5.CsrMatrix(A.rowptr, A.colidx, A.values, A.ncols) for A in mats]
+    xs = [torch.from_numpy(A.x).to(dev) for A in mats]
+    ys = [torch.empty(A.nrows, dtype=torch.float64, device=dev) for A in mats]
+
+    def plain_csr():
+        for C, x, y in zip(csrs, xs, ys):
+            C.spmv(x, y)
+    _, ms = time_launches(plain_csr, 5, 2)
+    plain_csr_us = _avg_us(ms)
+    res["plain_fp64_csr_us_per_vector"] = round(plain_csr_us, 1)
+    for C in csrs:
+        C.free()
+    del csrs
+    check = [int(i) for i in np.random.default_rng(1).choice(nmat, 4, replace=False)]
+    for dt, tdt in (("float64", torch.float64), ("float32", torch.float32)):
+        log(f"batch: autotune + convert {dt}")
+        Ms, shapes = [], {}
+        for A in mats:
+            (r, c), _ = autotune.choose_shape(A, dt)
+            shapes[f"{r},{c}"] = shapes.get(f"{r},{c}", 0) + 1
+            Ms.append(spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c, dt))
+        res[f"{dt} shapes"] = shapes
+        if dt == "float64":
+            log("batch: plain FP64 SPC5 launches")
+            def plain_spc5():
+                for M, x, y in zip(Ms, xs, ys):
+                    M.spmv(x, y)
+            _, ms = time_launches(plain_spc5, 5, 2)
+            res["plain_fp64_spc5_us_per_vector"] = round(_avg_us(ms), 1)
+        B = spc5.Spc5Batch(Ms)
+        for k in ks:
+            log(f"batch: {dt} k={k}")
+            rng = np.random.default_rng(k)
+            Xh = [rng.uniform(-1, 1, (A.ncols, k)) for A in mats]
+            Xs = [torch.from_numpy(X).to(dev, tdt) for X in Xh]
+            Ys = [torch.empty((A.nrows, k), dtype=tdt, device=dev) for A in mats]
+            B.set_operands(Xs, Ys)
+            _, ms = time_launches(B.run, 10, 3)
+            us = _avg_us(ms)
+            vb = 8 if dt == "float64" else 4
+            # matrix streamed once per launch + k vectors in and out
+            byts = sum(M.info.spmv_bytes - vb * (A.ncols + A.nrows) + k * vb * (A.ncols + A.nrows)
+                       for M, A in zip(Ms, mats))
+            errs = []
+            for i in check:
+                A = mats[i]
+                if dt == "float64":
+                    ref = oracle.csr_spmm(A.rowptr, A.colidx, A.values, Xh[i])
+                else:
+                    ref = oracle.csr_spmm(A.rowptr, A.colidx,
+                                          A.values.astype(np.float32).astype(np.float64),
+                                          Xh[i].astype(np.float32).astype(np.float64))
+                errs.append(oracle.rel_l2(Ys[i].cpu().double().numpy(), ref))
+            plain = k * plain_csr_us
+            res[f"{dt} k={k}"] = {
+                "launch_us": round(us, 1), "gflops": round(2.0 * nnz * k / us / 1e3, 1),
+                "gbs": round(byts / us / 1e3, 1), "frac_hbm": round(byts / us / 1e3 / PEAK_HBM_GBS, 4),
+                "speedup_vs_plain_fp64_csr": round(plain / us, 2),
+                "speedup_vs_plain_fp64_spc5": round(k * res["plain_fp64_spc5_us_per_vector"] / us, 2),
+                "max_rel_l2_sampled": max(errs), "sampled_matrices": check}
+            del Xs, Ys
+        B.free()
+        for M in Ms:
+            M.free()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,10 +406,24 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the primary format")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--skip", default="", help="comma list of extras to skip: "
+                    "kernels,formats,csr,flushed,fem,backward,batch")
+    ap.add_argument("--batch-mats", type=int, default=256)
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="before timing, negate a 1 GiB float64 buffer 3 times (a plain "
+                         "copy of known size for counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="host only: write the forward kernel's HBM traffic from two "
+                         "rocprofv3 --pmc counter files and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_write(args.traffic_from[0], args.traffic_from[1], args.workload)
+        return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: this library has no multi-GPU path, so "
+                                   "--gpus must be 1"}))
         raise SystemExit(2)
+    skip = set(filter(None, args.skip.split(",")))
 
     import numpy as np
     import torch
@@ -191,6 +449,13 @@ def main():
                 "frac_hbm": round(nbytes / (avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                 "bytes": int(nbytes), "rel_l2": err}, wall, ms
 
+    if args.calibration_copy:
+        src = torch.ones(COPY_ELEMS, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     log(f"converting to beta{rc}")
     M = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, *rc)
     nbytes = M.info.spmv_bytes
@@ -219,19 +484,29 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic_from_profiles(tag + f" beta({rc[0]},{rc[1]})"),
-                     "kernel": "k_spmv (spc5 forward)",
+                     "kernel": f"{FWD_KERNEL} (forward, kernel choice: {M.kernel})",
                      "algorithmic_bytes_per_launch": int(nbytes),
                      "avg_launch_us": round(avg_s * 1e6, 2)},
         "parity_rel_l2": prim["rel_l2"],
     }
-    if not args.no_extras:
-        other = "sweep" if M.kernel == "rows" else "rows"
-        log(f"timing the {other} kernel on beta{rc}")
-        M.set_schedule(other)
-        alt = measure(M, 50, 5, nbytes)[0]
-        M.set_schedule("auto")
-        out["kernels"] = {M.kernel: prim, other: alt}
+    extras = set() if args.no_extras else {"kernels", "formats", "csr", "flushed", "fem",
+                                           "backward", "batch"} - skip
+    if "kernels" in extras:
         prim["kernel"] = M.kernel
+        kern = {M.kernel: prim}
+        for other in ("staged", "sweep", "rows"):
+            if other == M.kernel:
+                continue
+            log(f"timing the {other} kernel on beta{rc}")
+            try:
+                M.set_schedule(other)
+            except spc5.Spc5Error as e:
+                kern[other] = {"unsupported": str(e)}
+                continue
+            kern[other] = measure(M, 50, 5, nbytes)[0]
+        M.set_schedule("auto")
+        out["kernels"] = kern
+    if "formats" in extras:
         formats = {f"beta({rc[0]},{rc[1]})": prim}
         for (r, c) in [(1, 8), (2, 4), (4, 4), (8, 8), (1, 16), (2, 8), (4, 8)]:
             if (r, c) == rc:
@@ -242,22 +517,43 @@ def main():
             formats[f"beta({r},{c})"]["fill"] = round(M2.info.fill, 4)
             formats[f"beta({r},{c})"]["kernel"] = M2.kernel
             M2.free()
+        # FP32 storage and accumulation at the same shape (error against the
+        # FP64 oracle on the original FP64 data)
+        log(f"timing float32 beta{rc}")
+        M3 = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, *rc, "float32")
+        x32 = x.float()
+        y32 = torch.empty(A.nrows, dtype=torch.float32, device=dev)
+        _, ms32 = time_launches(lambda: M3.spmv(x32, y32), 50, 5)
+        us32 = _avg_us(ms32)
+        formats[f"float32 beta({rc[0]},{rc[1]})"] = {
+            "gflops": round(flops / us32 / 1e3, 2), "launch_us": round(us32, 2),
+            "gbs": round(M3.info.spmv_bytes / us32 / 1e3, 1),
+            "frac_hbm": round(M3.info.spmv_bytes / us32 / 1e3 / PEAK_HBM_GBS, 4),
+            "bytes": int(M3.info.spmv_bytes),
+            "rel_l2_vs_fp64_oracle": oracle.rel_l2(y32.cpu().numpy(), yref),
+            "speedup_vs_fp64": round(prim["launch_us"] / us32, 3)}
+        M3.free()
+        out["formats"] = formats
+    if "csr" in extras:
         log("timing plain CSR")
         C = spc5.CsrMatrix(A.rowptr, A.colidx, A.values, A.ncols)
-        formats["csr"] = measure(C, 50, 5, C.spmv_bytes)[0]
+        out["csr"] = measure(C, 50, 5, C.spmv_bytes)[0]
         C.free()
+        out["speedup_vs_csr"] = round(out["csr"]["launch_us"] / prim["launch_us"], 3)
+    if "flushed" in extras:
         # cold-cache figure: a 1 GiB buffer is rewritten between launches
         # (outside the timed events), so the matrix cannot stay in the 256 MB
         # Infinity Cache
         scratch = torch.empty(1 << 27, dtype=torch.float64, device=dev)
-        flushed = measure(M, 30, 3, nbytes, flush=lambda: scratch.fill_(1.0))[0]
+        out["flushed"] = measure(M, 30, 3, nbytes, flush=lambda: scratch.fill_(1.0))[0]
         del scratch
-        out["formats"] = formats
-        out["flushed"] = flushed
-
-        out["speedup_vs_csr"] = round(formats["csr"]["launch_us"] / prim["launch_us"], 3)
-    if not args.no_extras and args.workload == "laplacian":
+    M.free()
+    if "fem" in extras and args.workload == "laplacian":
         out["fem"] = fem_extras(dev)
+    if "backward" in extras:
+        out["backward"] = backward_extras(dev)
+    if "batch" in extras:
+        out["batch"] = batch_extras(dev, args.batch_mats)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(A, rc, args.cpu_budget)
