@@ -268,13 +268,25 @@ def backward_extras(dev):
     vbar = torch.empty(G.nnz, dtype=torch.float32, device=dev)
     res = {"nrows": G.nrows, "nnz": G.nnz, "beta": [r, c], "fill": round(M.info.fill, 4),
            "dtype": "f32"}
-    for name, fn in (("forward", lambda: M.spmv_values(theta, x, y)),
-                     ("transpose", lambda: M.transpose(ybar, xbar, values=theta)),
-                     ("values_grad", lambda: M.values_grad(ybar, x, vbar))):
-        _, ms = time_launches(fn, 30, 5)
+    def timed(fn, n=30):
+        _, ms = time_launches(fn, n, 5)
         us = _avg_us(ms)
-        res[name] = {"launch_us": round(us, 2), "gbs": round(nb / us / 1e3, 1),
-                     "frac_hbm": round(nb / us / 1e3 / PEAK_HBM_GBS, 4)}
+        return {"launch_us": round(us, 2), "gbs": round(nb / us / 1e3, 1),
+                "frac_hbm": round(nb / us / 1e3 / PEAK_HBM_GBS, 4)}
+    res["forward"] = timed(lambda: M.spmv_values(theta, x, y))
+    res["values_grad"] = timed(lambda: M.values_grad(ybar, x, vbar))
+    # masked scatter with atomics (no plan): serialises on popular columns
+    res["transpose_scatter"] = timed(lambda: M.transpose(ybar, xbar, values=theta), 5)
+    t0 = time.perf_counter()
+    M.prepare_transpose()
+    res["transpose_plan_build_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    res["transpose_plan"] = {"beta": [M.info.transpose_r, M.info.transpose_c],
+                             "kernel": {1: "rows", 2: "sweep", 3: "staged"}.get(
+                                 M.info.transpose_kernel)}
+    # through the plan: caller theta gathered to A^T order, then the forward
+    # kernel over A^T (both launches inside the timed region)
+    res["transpose"] = timed(lambda: M.transpose(ybar, xbar, values=theta))
+    res["transpose_own_values"] = timed(lambda: M.transpose(ybar, xbar))
     res["fwd_bwd_us"] = round(sum(res[k]["launch_us"]
                                   for k in ("forward", "transpose", "values_grad")), 2)
     # one full autograd step, wall clock

@@ -33,9 +33,14 @@
  *    Compute calls are asynchronous on that stream; argument checks are
  *    synchronous.
  *  - A matrix handle is immutable after creation except for its schedule
- *    (spc5_set_schedule); concurrent compute calls on one handle from several
- *    streams are allowed.  The caller must not free a handle while work that
- *    uses it is pending.
+ *    (spc5_set_schedule) and its transpose plan (spc5_prepare_transpose).
+ *    Compute calls on one handle may overlap on several streams, with two
+ *    exceptions that share a buffer held by the handle: forward products of
+ *    a matrix whose staged schedule splits long panels
+ *    (spc5_info.split_panels > 0: the pieces' partial sums), and transposes
+ *    with caller values through a plan.  Those must be ordered (one stream
+ *    or synchronised streams).  The caller must not free a handle while
+ *    work that uses it is pending.
  *  - Calls must be made with the HIP device that was current at creation.
  */
 #ifndef SPC5_H
@@ -76,6 +81,14 @@ typedef struct {
     int64_t spmv_bytes;       /* algorithmic bytes moved by one y = A x:
                                  values + anchors + masks + blk_ptr + x + y */
     int64_t device_bytes;     /* device memory held by the handle */
+    /* transposed-product plan (spc5_prepare_transpose); all 0 without one */
+    int transpose_r, transpose_c; /* beta(r,c) of the stored A^T */
+    int transpose_kernel;     /* forward kernel run over A^T (spc5_kernel) */
+    int transpose_pad;        /* reserved, 0 */
+    int64_t transpose_bytes;  /* algorithmic bytes of one x_bar = A^T y_bar
+                                 through the plan (without the value gather) */
+    int64_t split_panels;     /* panels longer than one staged tile, cut into
+                                 pieces on several workgroups (0: none) */
 } spc5_info;
 
 /* ---------------------------------------------------------------- creation */
@@ -152,15 +165,34 @@ int spc5_spmv(const spc5_matrix *A, const void *x, void *y, void *stream);
 int spc5_spmv_values(const spc5_matrix *A, const void *values, const void *x,
                      void *y, void *stream);
 
-/* xbar[0..ncols) = A^T ybar[0..nrows): the transposed product, scattered from
- * the SPC5 blocks (each set mask bit adds value * ybar[row] to
- * xbar[anchor+k]).  xbar is overwritten (zeroed on the stream first).
- * values: device packed values, or NULL for the matrix's own.  The
- * accumulation order varies between runs (atomic adds).  Device pointers. */
+/* xbar[0..ncols) = A^T ybar[0..nrows), the transposed product (the backward
+ * of y = A x; the paper defines only the forward product, Algorithm 1).
+ * xbar is overwritten.  values: device packed values (A's packed order), or
+ * NULL for the matrix's own.  Device pointers.
+ * Without a plan: masked scatter from A's blocks (each set mask bit adds
+ * value * ybar[row] to xbar[anchor+k] with a float atomic; xbar is zeroed on
+ * the stream first); the accumulation order varies between runs.
+ * With a plan (spc5_prepare_transpose): the forward kernel over the stored
+ * A^T; no atomics, the result is reproducible bit for bit.  When `values` is
+ * given, the plan first moves them to A^T's order in a buffer owned by A, so
+ * such calls on one handle must not overlap in time (one stream, or
+ * synchronised streams). */
 int spc5_spmv_transpose(const spc5_matrix *A, const void *ybar, void *xbar,
                         void *stream);
 int spc5_spmv_transpose_values(const spc5_matrix *A, const void *values,
                                const void *ybar, void *xbar, void *stream);
+
+/* Build the transposed-product plan of A: A^T converted on the device to
+ * SPC5 beta(r,c) storage (r = c = 0: A's own shape) plus, for each of its
+ * packed values, the packed index of the same entry in A.  Afterwards
+ * spc5_spmv_transpose* run as a forward product over A^T.  Costs about the
+ * device memory of A once more (values twice: A^T's own and the gather
+ * buffer) plus 4 bytes per nonzero; held until spc5_free.  Synchronous.
+ * Calling it again with the same shape is a no-op.
+ * Errors: SPC5_EINVAL (NULL A, a plan with another shape exists),
+ * SPC5_EUNSUPPORTED (r or c out of range, A^T's block count >= 2^31),
+ * SPC5_ENOMEM, SPC5_EDEVICE. */
+int spc5_prepare_transpose(spc5_matrix *A, int r, int c);
 
 /* Gradient of <ybar, A(theta) x> with respect to the packed values theta:
  * vbar[v] = ybar[row(v)] * x[col(v)], in packed order (nnz entries).

@@ -3,7 +3,9 @@
 theta holds the matrix's nonzeros in SPC5 packed order (the order of
 Spc5Matrix.export()); the sparsity pattern (anchors and masks) is fixed.
 Backward, both in HIP kernels of libspc5:
-  xbar     = A(theta)^T ybar   (masked scatter-transpose, spc5_spmv_transpose)
+  xbar     = A(theta)^T ybar   (spc5_spmv_transpose_values: the forward kernel
+                                over the stored A^T when the matrix has a
+                                transpose plan, else the masked scatter)
   thetabar = ybar[row(v)] * x[col(v)] in packed order (spc5_values_grad)
 This module only wires the calls; it computes nothing itself.
 """
@@ -48,8 +50,10 @@ class Spc5Linear(torch.nn.Module):
     forward(x) = A(theta) x for a vector x of length ncols.
     """
 
-    def __init__(self, A: Spc5Matrix, theta: torch.Tensor):
+    def __init__(self, A: Spc5Matrix, theta: torch.Tensor, transpose_plan: bool = True):
         super().__init__()
+        if transpose_plan:
+            A.prepare_transpose()
         self.A = A
         self.theta = torch.nn.Parameter(theta)
 

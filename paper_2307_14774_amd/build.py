@@ -18,7 +18,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libspc5.so")
-SOURCES = ["api.hip", "convert.hip", "spmv.hip", "staged.hip", "backward.hip", "spmm.hip", "batch.hip"]
+SOURCES = ["api.hip", "convert.hip", "spmv.hip", "staged.hip", "backward.hip", "spmm.hip", "batch.hip",
+           "transpose_plan.hip"]
 ARCH = os.environ.get("SPC5_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

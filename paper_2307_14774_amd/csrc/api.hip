@@ -47,13 +47,20 @@ bool x_fits_buffer(const spc5_matrix *A) {
 }
 
 int auto_kernel(const spc5_matrix *A) {
-    // The staged kernel needs every panel to fit one LDS staging window;
-    // matrices with a longer panel use the sweep kernel (one lane per block
-    // row, segmented reduction), which takes panels of any length.
-    // beta(1,c): one row per block, no x window to share; the sweep kernel
-    // handles it as well or better
-    return A->staged_ok && x_fits_buffer(A) && A->r > 1 ? SPC5_KERNEL_STAGED
-                                                        : SPC5_KERNEL_SWEEP;
+    // Staged for r > 1 (the r rows of a block share its x window).  For
+    // beta(1,c) the sweep kernel is faster, unless a panel is longer than a
+    // tile: only the staged schedule splits such panels across workgroups.
+    // The staged and row kernels address x through a 2 GiB buffer range.
+    if (!A->staged_ok || !x_fits_buffer(A)) return SPC5_KERNEL_SWEEP;
+    return A->r > 1 || A->nsplit > 0 ? SPC5_KERNEL_STAGED : SPC5_KERNEL_SWEEP;
+}
+
+int finish_matrix(spc5_matrix *A) {
+    A->ppt = default_ppt(A->npanels ? (double)A->nblocks * A->r / (double)A->npanels : 0.0);
+    const int st = build_staged_schedule(A, 0);
+    if (st != SPC5_OK) return st;
+    A->kernel = auto_kernel(A);
+    return SPC5_OK;
 }
 
 // Lanes per row of the CSR-vector comparison kernel: the power of two
@@ -144,17 +151,18 @@ struct DeviceGuard {
     }
 };
 
-static void free_matrix(spc5_matrix *A) {
+void free_matrix(spc5_matrix *A) {
     if (!A) return;
     DeviceGuard g(A->device);
+    free_matrix(A->tr);
+    if (A->tr_perm) (void)hipFree(A->tr_perm);
+    if (A->tr_vals) (void)hipFree(A->tr_vals);
     if (A->blk_ptr) (void)hipFree(A->blk_ptr);
     if (A->blk_col) (void)hipFree(A->blk_col);
     if (A->masks) (void)hipFree(A->masks);
     if (A->val) (void)hipFree(A->val);
     if (A->panel_val) (void)hipFree(A->panel_val);
-    if (A->tile_p) (void)hipFree(A->tile_p);
-    if (A->tile_b) (void)hipFree(A->tile_b);
-    if (A->tile_v) (void)hipFree(A->tile_v);
+    free_staged_schedule(A);
     delete A;
 }
 
@@ -218,9 +226,7 @@ int csr_to_spc5(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32
     st = convert_on_device(A, d_rowptr, d_colidx, d_val);
     drop();
     if (st != SPC5_OK) { free_matrix(A); return st; }
-    A->ppt = default_ppt(npanels ? (double)A->nblocks * r / (double)npanels : 0.0);
-    if ((st = build_staged_schedule(A, 0)) != SPC5_OK) { free_matrix(A); return st; }
-    A->kernel = auto_kernel(A);
+    if ((st = finish_matrix(A)) != SPC5_OK) { free_matrix(A); return st; }
     *out = A;
     return SPC5_OK;
 }
@@ -245,6 +251,15 @@ int spc5_get_info(const spc5_matrix *A, spc5_info *out) {
                       4 * (A->npanels + 1) + vb * A->ncols + vb * A->nrows;
     out->device_bytes = vb * A->nnz + 4 * A->nblocks + (int64_t)A->r * A->mask_bytes * A->nblocks +
                         8 * (A->npanels + 1);
+    out->split_panels = A->kernel == SPC5_KERNEL_STAGED ? A->nsplit : 0;
+    if (const spc5_matrix *T = A->tr) {
+        out->transpose_r = T->r;
+        out->transpose_c = T->c;
+        out->transpose_kernel = T->kernel;
+        out->transpose_bytes = vb * T->nnz + 4 * T->nblocks +
+                               (int64_t)T->r * T->mask_bytes * T->nblocks + 4 * (T->npanels + 1) +
+                               vb * T->ncols + vb * T->nrows;
+    }
     return SPC5_OK;
 }
 
@@ -331,8 +346,25 @@ int spc5_spmv_transpose_values(const spc5_matrix *A, const void *values, const v
     int st = compute_guard(A, {{ybar, A ? A->nrows : 0}, {xbar, A ? A->ncols : 0}});
     if (st) return st;
     DeviceGuard g(A->device);
-    hipError_t e = launch_transpose(A, values ? values : A->val, ybar, xbar, (hipStream_t)stream);
+    hipError_t e = A->tr ? launch_transpose_plan(A, values, ybar, xbar, (hipStream_t)stream)
+                         : launch_transpose(A, values ? values : A->val, ybar, xbar,
+                                            (hipStream_t)stream);
     return e == hipSuccess ? SPC5_OK : hip_fail(e, "spc5_spmv_transpose launch");
+}
+
+int spc5_prepare_transpose(spc5_matrix *A, int r, int c) {
+    if (!A) return fail(SPC5_EINVAL, "A is NULL");
+    if (r == 0) r = A->r;
+    if (c == 0) c = A->c;
+    if (r < 1 || r > 8 || c < 1 || c > 16)
+        return fail(SPC5_EUNSUPPORTED, "beta(%d,%d) is out of range", r, c);
+    if (A->tr) {
+        if (A->tr->r == r && A->tr->c == c) return SPC5_OK;
+        return fail(SPC5_EINVAL, "a transpose plan with another shape exists");
+    }
+    DeviceGuard g(A->device);
+    if (!g.ok) return fail(SPC5_EDEVICE, "cannot select the matrix's device");
+    return build_transpose_plan(A, r, c);
 }
 
 int spc5_values_grad(const spc5_matrix *A, const void *ybar, const void *x, void *vbar,

@@ -234,7 +234,8 @@ int count_blocks_device(const int64_t *d_rowptr, const int32_t *d_colidx, int64_
 }
 
 int convert_on_device(spc5_matrix *A, const int64_t *d_rowptr, const int32_t *d_colidx,
-                      const void *d_values) {
+                      const void *d_values, const int32_t *d_payload,
+                      int32_t *d_payload_out) {
     hipStream_t s = nullptr;
     hipError_t e;
     int64_t *count = nullptr, *bptr64 = nullptr, *scratch = nullptr;
@@ -296,6 +297,25 @@ int convert_on_device(spc5_matrix *A, const int64_t *d_rowptr, const int32_t *d_
         hipSuccess) {
         cleanup();
         return hip_fail(e, "filling SPC5 arrays");
+    }
+    if (d_payload && d_payload_out && A->npanels > 0) {
+        // the same walk once more with an int32 payload in place of the
+        // values (anchors and masks are rewritten with identical contents)
+        const unsigned grid = (unsigned)((A->npanels + 255) / 256);
+        if (A->mask_bytes == 1)
+            hipLaunchKernelGGL((k_block_panels<true, int32_t, uint8_t>), dim3(grid), dim3(256), 0,
+                               s, A->nrows, A->npanels, A->r, A->c, d_rowptr, d_colidx,
+                               d_payload, (int64_t *)nullptr, bptr64, A->blk_col,
+                               (uint8_t *)A->masks, d_payload_out);
+        else
+            hipLaunchKernelGGL((k_block_panels<true, int32_t, uint16_t>), dim3(grid), dim3(256),
+                               0, s, A->nrows, A->npanels, A->r, A->c, d_rowptr, d_colidx,
+                               d_payload, (int64_t *)nullptr, bptr64, A->blk_col,
+                               (uint16_t *)A->masks, d_payload_out);
+        if ((e = hipGetLastError()) != hipSuccess) {
+            cleanup();
+            return hip_fail(e, "placing the payload");
+        }
     }
     hipLaunchKernelGGL(k_narrow, dim3((unsigned)((np1 + 255) / 256)), dim3(256), 0, s,
                        A->npanels, A->nrows, A->r, bptr64, d_rowptr, A->blk_ptr,

@@ -24,9 +24,19 @@ struct spc5_matrix {
     int32_t *panel_val = nullptr;  // [npanels+1], value offset of each panel
     // staged-kernel tile schedule: first panel / block / value of each tile
     int32_t *tile_p = nullptr, *tile_b = nullptr, *tile_v = nullptr;   // [ntiles_staged+1]
+    int32_t *tile_f = nullptr;     // [ntiles_staged+1], 1: piece of a split panel
     int64_t ntiles_staged = 0;
     int max_tile_values = 0;       // largest tile, in values
-    bool staged_ok = false;        // every panel fits one staging window
+    bool staged_ok = false;        // the staged schedule exists
+    // panels longer than a tile: panel, first and last piece tile
+    int32_t *split_p = nullptr, *split_t0 = nullptr, *split_t1 = nullptr;   // [nsplit]
+    int64_t nsplit = 0;
+    void *partial = nullptr;       // [ntiles_staged * r] partial row sums of pieces
+    // transposed-product plan (spc5_prepare_transpose): A^T in beta(r,c) and,
+    // for each of its packed values, the packed index of the same entry in A
+    spc5_matrix *tr = nullptr;
+    int32_t *tr_perm = nullptr;    // [nnz]
+    void *tr_vals = nullptr;       // [nnz] gather buffer for caller values
 };
 
 struct spc5_csr {
@@ -68,6 +78,7 @@ hipError_t launch_spmv_staged(const spc5_matrix *A, const void *val, const void 
 // (Re)build the staged kernel's tile schedule with at most ppw panels per tile
 // (0: as many as one workgroup has rows for).
 int build_staged_schedule(spc5_matrix *A, int ppw);
+void free_staged_schedule(spc5_matrix *A);
 hipError_t excl_scan_i64(const int64_t *in, int64_t n, int64_t *out, hipStream_t s,
                          int64_t **scratch);
 int remap_enabled();
@@ -79,9 +90,21 @@ hipError_t launch_transpose(const spc5_matrix *A, const void *val, const void *y
 hipError_t launch_values_grad(const spc5_matrix *A, const void *ybar, const void *x,
                               void *vbar, hipStream_t s);
 
-// CSR -> SPC5 conversion on the device (d_* are device CSR arrays).
+// CSR -> SPC5 conversion on the device (d_* are device CSR arrays).  When
+// d_payload is given, d_payload_out[nnz] receives it in packed order (the
+// same placement as the values).
 int convert_on_device(spc5_matrix *A, const int64_t *d_rowptr, const int32_t *d_colidx,
-                      const void *d_values);
+                      const void *d_values, const int32_t *d_payload = nullptr,
+                      int32_t *d_payload_out = nullptr);
+// Release every device array of A (and of its transposed plan) and A itself.
+void free_matrix(spc5_matrix *A);
+// Default schedule and kernel choice of a freshly converted matrix.
+int finish_matrix(spc5_matrix *A);
+// Transposed-product plan of A (see spc5_prepare_transpose).
+int build_transpose_plan(spc5_matrix *A, int r, int c);
+// x_out = A^T y_in through the plan; vals overrides A's values (packed order).
+hipError_t launch_transpose_plan(const spc5_matrix *A, const void *vals, const void *ybar,
+                                 void *xbar, hipStream_t s);
 
 // Fill `n` elements of a device array with zero using a kernel (safe to
 // record in a graph).

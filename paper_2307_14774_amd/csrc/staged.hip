@@ -24,9 +24,10 @@
 //  5. a butterfly over the S sub-lanes, one store per row.
 //
 // Tiles come from a schedule built at conversion (at most 256/r panels, VT
-// values and BT blocks per tile); a matrix with a single panel larger than a
-// tile uses the sweep kernel.  No atomics: results are reproducible bit for
-// bit.
+// values and BT blocks per tile).  A panel larger than a tile is cut into
+// piece tiles spread over the grid (load balance for very long rows); their
+// partial row sums are added in tile order by a small fixup kernel.  No
+// atomics: results are reproducible bit for bit.
 #include "spc5_internal.h"
 #include "wave.h"
 
@@ -210,9 +211,11 @@ template <typename T, int R, int C, int NVG>
 __global__ __launch_bounds__(kWG) void k_spmv_stream(
     int64_t nrows, int64_t ncols, int64_t ntiles, int tiles_per_wg, int64_t nwg, int remap,
     const int32_t *__restrict__ tile_p, const int32_t *__restrict__ tile_b,
-    const int32_t *__restrict__ tile_v, const int32_t *__restrict__ blk_ptr,
+    const int32_t *__restrict__ tile_v, const int32_t *__restrict__ tile_f,
+    const int32_t *__restrict__ blk_ptr,
     const int32_t *__restrict__ blk_col, const typename MaskOf<C>::type *__restrict__ masks,
-    const T *__restrict__ val, const T *__restrict__ x, T *__restrict__ y)
+    const T *__restrict__ val, const T *__restrict__ x, T *__restrict__ y,
+    T *__restrict__ partial)
 {
     using Cfg = StreamCfg<T, R, C, NVG>;
     constexpr int U = Cfg::U, BT = Cfg::BT;
@@ -232,7 +235,9 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
     const int64_t t_end = min(t_begin + tiles_per_wg, ntiles);
     const Buf xbuf = make_buf(x, ncols * (int64_t)sizeof(T));
 
-    int p0 = tile_p[t_begin], p1 = tile_p[t_begin + 1];
+    // a piece tile (part of a panel longer than a tile) covers that one panel
+    int f0 = tile_f[t_begin];
+    int p0 = tile_p[t_begin], p1 = f0 ? p0 + 1 : tile_p[t_begin + 1];
     int b0 = tile_b[t_begin], b1 = tile_b[t_begin + 1];
     int v0 = tile_v[t_begin], v1 = tile_v[t_begin + 1];
     TileStage<T, R, C, NVG> st;
@@ -242,7 +247,8 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
         // next tile's bounds (scalar loads, their own counter)
         const bool more = t + 1 < t_end;
         const int64_t tn = more ? t + 1 : t;
-        const int q0 = tile_p[tn], q1 = tile_p[tn + 1];
+        const int g0 = tile_f[tn];
+        const int q0 = tile_p[tn], q1 = g0 ? q0 + 1 : tile_p[tn + 1];
         const int c0 = tile_b[tn], c1 = tile_b[tn + 1];
         const int w0 = tile_v[tn], w1 = tile_v[tn + 1];
 
@@ -308,8 +314,9 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
         const int lps = S * R;
         const int pl = th / lps, sub = (th / R) & (S - 1), i = th % R;
         const bool live = pl < np;
-        const int bs = live ? sbp[pl] - b0 : 0;
-        const int be = live ? sbp[pl + 1] - b0 : 0;
+        // a piece tile holds only part of its panel's blocks: clamp
+        const int bs = live ? max(sbp[pl], b0) - b0 : 0;
+        const int be = live ? min(sbp[pl + 1], b1) - b0 : 0;
         T acc = T(0);
         for (int b = bs + sub; b < be; b += U * S) {
             unsigned m[U];
@@ -340,123 +347,220 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
         for (int d = R; d < lps; d <<= 1) acc += __shfl_xor(acc, d);
         if (live && sub == 0) {
             const int64_t row = (int64_t)(p0 + pl) * R + i;
-            if (row < nrows) y[row] = acc;
+            if (f0) partial[t * R + i] = acc;     // summed by k_split_fixup
+            else if (row < nrows) y[row] = acc;
         }
-        p0 = q0; p1 = q1; b0 = c0; b1 = c1; v0 = w0; v1 = w1;
+        f0 = g0; p0 = q0; p1 = q1; b0 = c0; b1 = c1; v0 = w0; v1 = w1;
     }
 }
 
 // ---------------------------------------------------------------- schedule
 
 // Greedy tiles inside each group of ppw consecutive panels: a panel starts a
-// new tile when adding it would pass vt values or bt blocks.  One thread per
-// group; pass 0 counts the tiles of each group, pass 1 writes them.  A panel
-// larger than a whole tile sets *bad.
-__global__ void k_tile_groups(int pass, int64_t npanels, int ppw, int vt, int bt,
-                              const int32_t *bp, const int32_t *pv, int64_t *count,
-                              const int64_t *first, int32_t *tp, int32_t *tb, int32_t *tv,
-                              int *bad, int *maxvals) {
+// new tile when adding it would pass vt values or bt blocks.  A panel larger
+// than a whole tile is cut into pieces of at most vt values and bt blocks,
+// each a tile of its own flagged as a piece; the pieces' partial row sums
+// are added in tile order by k_split_fixup, so the result stays
+// reproducible.  One thread per group; pass 0 counts the tiles and the split
+// panels of each group, pass 1 writes them.
+template <typename MT>
+__global__ void k_tile_groups(int pass, int64_t npanels, int r, int ppw, int vt, int bt,
+                              const int32_t *bp, const int32_t *pv, const MT *masks,
+                              int64_t *count, const int64_t *first, int64_t *scount,
+                              const int64_t *sfirst, int32_t *tp, int32_t *tb, int32_t *tv,
+                              int32_t *tf, int32_t *sp, int32_t *st0, int32_t *st1,
+                              int *maxvals) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t ng = (npanels + ppw - 1) / ppw;
     if (g >= ng) return;
     const int64_t pa = g * ppw, pz = min(pa + ppw, npanels);
     int64_t n = 0, o = pass ? first[g] : 0;
-    int64_t start = pa;
+    int64_t ns = 0, so = pass ? sfirst[g] : 0;
+    int64_t start = -1;   // first panel of the open tile, -1: none open
+    auto emit = [&](int64_t p, int b, int v, int flag) {
+        if (pass) {
+            tp[o + n] = (int32_t)p;
+            tb[o + n] = b;
+            tv[o + n] = v;
+            tf[o + n] = flag;
+        }
+        ++n;
+    };
     for (int64_t p = pa; p < pz; ++p) {
-        if (pv[p + 1] - pv[p] > vt || bp[p + 1] - bp[p] > bt) atomicOr(bad, 1);
-        const bool cut = p > start && (pv[p + 1] - pv[start] > vt || bp[p + 1] - bp[start] > bt);
-        if (p == pa || cut) {
+        if (pv[p + 1] - pv[p] > vt || bp[p + 1] - bp[p] > bt) {
+            if (start >= 0) atomicMax(maxvals, pv[p] - pv[start]);
+            start = -1;
             if (pass) {
-                tp[o + n] = (int32_t)p;
-                tb[o + n] = bp[p];
-                tv[o + n] = pv[p];
+                sp[so + ns] = (int32_t)p;
+                st0[so + ns] = (int32_t)(o + n);
             }
-            if (p > pa) atomicMax(maxvals, pv[p] - pv[start]);
-            ++n;
+            int v = pv[p], pb = bp[p], pvv = pv[p];
+            emit(p, pb, pvv, 1);
+            for (int b = bp[p]; b < bp[p + 1]; ++b) {
+                int cnt = 0;
+                for (int i = 0; i < r; ++i) cnt += __popc((unsigned)masks[(int64_t)b * r + i]);
+                if (b + 1 - pb > bt || v + cnt - pvv > vt) {
+                    atomicMax(maxvals, v - pvv);
+                    pb = b;
+                    pvv = v;
+                    emit(p, pb, pvv, 1);
+                }
+                v += cnt;
+            }
+            atomicMax(maxvals, v - pvv);
+            if (pass) st1[so + ns] = (int32_t)(o + n - 1);
+            ++ns;
+            continue;
+        }
+        const bool cut =
+            start >= 0 && (pv[p + 1] - pv[start] > vt || bp[p + 1] - bp[start] > bt);
+        if (start < 0 || cut) {
+            if (start >= 0) atomicMax(maxvals, pv[p] - pv[start]);
+            emit(p, bp[p], pv[p], 0);
             start = p;
         }
     }
-    atomicMax(maxvals, pv[pz] - pv[start]);
-    if (!pass) count[g] = n;
+    if (start >= 0) atomicMax(maxvals, pv[pz] - pv[start]);
+    if (!pass) {
+        count[g] = n;
+        scount[g] = ns;
+    }
 }
 
 __global__ void k_tile_sentinel(int64_t npanels, int64_t ntiles, const int32_t *bp,
-                                const int32_t *pv, int32_t *tp, int32_t *tb, int32_t *tv) {
+                                const int32_t *pv, int32_t *tp, int32_t *tb, int32_t *tv,
+                                int32_t *tf) {
     tp[ntiles] = (int32_t)npanels;
     tb[ntiles] = bp[npanels];
     tv[ntiles] = pv[npanels];
+    tf[ntiles] = 0;
+}
+
+// Rows of a split panel: the partial sums of its pieces, in tile order.
+template <typename T>
+__global__ void k_split_fixup(int64_t nsplit, int r, int64_t nrows, const int32_t *sp,
+                              const int32_t *st0, const int32_t *st1, const T *partial, T *y) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nsplit * r) return;
+    const int64_t s = q / r;
+    const int i = (int)(q % r);
+    const int64_t row = (int64_t)sp[s] * r + i;
+    if (row >= nrows) return;
+    T acc = T(0);
+    for (int64_t t = st0[s]; t <= st1[s]; ++t) acc += partial[t * r + i];
+    y[row] = acc;
+}
+
+template <typename MT>
+static void launch_tile_groups(unsigned grid, int pass, const spc5_matrix *A, int ppw, int vt,
+                               int bt, int64_t *count, const int64_t *first, int64_t *scount,
+                               const int64_t *sfirst, int32_t *tp, int32_t *tb, int32_t *tv,
+                               int32_t *tf, int32_t *sp, int32_t *st0, int32_t *st1,
+                               int *maxvals) {
+    hipLaunchKernelGGL(k_tile_groups<MT>, dim3(grid), dim3(256), 0, nullptr, pass, A->npanels,
+                       A->r, ppw, vt, bt, A->blk_ptr, A->panel_val, (const MT *)A->masks,
+                       count, first, scount, sfirst, tp, tb, tv, tf, sp, st0, st1, maxvals);
+}
+
+void free_staged_schedule(spc5_matrix *A) {
+    for (int32_t **p : {&A->tile_p, &A->tile_b, &A->tile_v, &A->tile_f, &A->split_p,
+                        &A->split_t0, &A->split_t1}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    if (A->partial) (void)hipFree(A->partial);
+    A->partial = nullptr;
+    A->ntiles_staged = 0;
+    A->nsplit = 0;
 }
 
 int build_staged_schedule(spc5_matrix *A, int ppw_req) {
-    if (A->tile_p) { (void)hipFree(A->tile_p); A->tile_p = nullptr; }
-    if (A->tile_b) { (void)hipFree(A->tile_b); A->tile_b = nullptr; }
-    if (A->tile_v) { (void)hipFree(A->tile_v); A->tile_v = nullptr; }
-    A->ntiles_staged = 0;
+    free_staged_schedule(A);
     A->staged_ok = true;
     int vt, bt, ppw;
     staged_caps(A, &vt, &bt, &ppw);
     if (ppw_req > 0) ppw = std::min(ppw, ppw_req);
     A->sppt = ppw;
+    A->max_tile_values = 0;
     if (A->npanels == 0) return SPC5_OK;
     hipStream_t s = nullptr;
     hipError_t e;
-    int64_t *count = nullptr, *first = nullptr, *scratch = nullptr;
-    int *bad = nullptr;
-    int status = SPC5_OK;
-    A->max_tile_values = 0;
+    int64_t *count = nullptr, *first = nullptr, *scount = nullptr, *sfirst = nullptr;
+    int64_t *scratch = nullptr, *scratch2 = nullptr;
+    int *maxv = nullptr;
     auto cleanup = [&]() {
-        if (count) (void)hipFree(count);
-        if (first) (void)hipFree(first);
-        if (scratch) (void)hipFree(scratch);
-        if (bad) (void)hipFree(bad);
+        for (void *p : {(void *)count, (void *)first, (void *)scount, (void *)sfirst,
+                        (void *)scratch, (void *)scratch2, (void *)maxv})
+            if (p) (void)hipFree(p);
+    };
+    auto bail = [&](hipError_t err, const char *what) {
+        cleanup();
+        free_staged_schedule(A);
+        return hip_fail(err, what);
     };
     const int64_t np = A->npanels;
     const int64_t ng = (np + ppw - 1) / ppw;
     const unsigned grid = (unsigned)((ng + 255) / 256);
+    const bool m8 = A->mask_bytes == 1;
     if ((e = hipMalloc((void **)&count, (size_t)ng * 8)) != hipSuccess ||
         (e = hipMalloc((void **)&first, (size_t)(ng + 1) * 8)) != hipSuccess ||
-        (e = hipMalloc((void **)&bad, 8)) != hipSuccess) {
-        cleanup();
-        return hip_fail(e, "allocating the tile schedule");
-    }
-    if ((e = zero_fill(bad, 2, 4, s)) != hipSuccess) {
-        cleanup();
-        return hip_fail(e, "clearing the schedule flag");
-    }
-    hipLaunchKernelGGL(k_tile_groups, dim3(grid), dim3(256), 0, s, 0, np, ppw, vt, bt,
-                       A->blk_ptr, A->panel_val, count, (const int64_t *)nullptr,
-                       (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr, bad, bad + 1);
+        (e = hipMalloc((void **)&scount, (size_t)ng * 8)) != hipSuccess ||
+        (e = hipMalloc((void **)&sfirst, (size_t)(ng + 1) * 8)) != hipSuccess ||
+        (e = hipMalloc((void **)&maxv, 8)) != hipSuccess)
+        return bail(e, "allocating the tile schedule");
+    if ((e = zero_fill(maxv, 1, 4, s)) != hipSuccess) return bail(e, "clearing the schedule");
+    if (m8)
+        launch_tile_groups<uint8_t>(grid, 0, A, ppw, vt, bt, count, nullptr, scount, nullptr,
+                                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                    nullptr, maxv);
+    else
+        launch_tile_groups<uint16_t>(grid, 0, A, ppw, vt, bt, count, nullptr, scount, nullptr,
+                                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                     nullptr, maxv);
     if ((e = hipGetLastError()) != hipSuccess ||
-        (e = excl_scan_i64(count, ng, first, s, &scratch)) != hipSuccess) {
-        cleanup();
-        return hip_fail(e, "counting tiles");
-    }
-    int64_t ntiles = 0;
-    int hbad[2] = {0, 0};
+        (e = excl_scan_i64(count, ng, first, s, &scratch)) != hipSuccess ||
+        (e = excl_scan_i64(scount, ng, sfirst, s, &scratch2)) != hipSuccess)
+        return bail(e, "counting tiles");
+    int64_t ntiles = 0, nsplit = 0;
     if ((e = hipMemcpy(&ntiles, first + ng, 8, hipMemcpyDeviceToHost)) != hipSuccess ||
-        (e = hipMemcpy(hbad, bad, 8, hipMemcpyDeviceToHost)) != hipSuccess) {
+        (e = hipMemcpy(&nsplit, sfirst + ng, 8, hipMemcpyDeviceToHost)) != hipSuccess)
+        return bail(e, "reading the tile count");
+    if (ntiles >= ((int64_t)1 << 31)) {
         cleanup();
-        return hip_fail(e, "reading the tile count");
+        free_staged_schedule(A);
+        return fail(SPC5_EUNSUPPORTED, "too many tiles");
     }
-    A->staged_ok = hbad[0] == 0;
-    A->max_tile_values = hbad[1];
-    const size_t nt1 = (size_t)ntiles + 1;
+    const size_t nt1 = (size_t)ntiles + 1, ns1 = (size_t)std::max<int64_t>(nsplit, 1);
+    const int vb = A->dtype == SPC5_F64 ? 8 : 4;
     if ((e = hipMalloc((void **)&A->tile_p, nt1 * 4 + kPad)) != hipSuccess ||
         (e = hipMalloc((void **)&A->tile_b, nt1 * 4 + kPad)) != hipSuccess ||
-        (e = hipMalloc((void **)&A->tile_v, nt1 * 4 + kPad)) != hipSuccess) {
-        cleanup();
-        return hip_fail(e, "allocating the tile schedule");
-    }
-    hipLaunchKernelGGL(k_tile_groups, dim3(grid), dim3(256), 0, s, 1, np, ppw, vt, bt,
-                       A->blk_ptr, A->panel_val, (int64_t *)nullptr, first, A->tile_p,
-                       A->tile_b, A->tile_v, bad, bad + 1);
+        (e = hipMalloc((void **)&A->tile_v, nt1 * 4 + kPad)) != hipSuccess ||
+        (e = hipMalloc((void **)&A->tile_f, nt1 * 4 + kPad)) != hipSuccess ||
+        (e = hipMalloc((void **)&A->split_p, ns1 * 4)) != hipSuccess ||
+        (e = hipMalloc((void **)&A->split_t0, ns1 * 4)) != hipSuccess ||
+        (e = hipMalloc((void **)&A->split_t1, ns1 * 4)) != hipSuccess ||
+        (nsplit > 0 &&
+         (e = hipMalloc(&A->partial, nt1 * (size_t)A->r * vb)) != hipSuccess))
+        return bail(e, "allocating the tile schedule");
+    if (m8)
+        launch_tile_groups<uint8_t>(grid, 1, A, ppw, vt, bt, nullptr, first, nullptr, sfirst,
+                                    A->tile_p, A->tile_b, A->tile_v, A->tile_f, A->split_p,
+                                    A->split_t0, A->split_t1, maxv);
+    else
+        launch_tile_groups<uint16_t>(grid, 1, A, ppw, vt, bt, nullptr, first, nullptr, sfirst,
+                                     A->tile_p, A->tile_b, A->tile_v, A->tile_f, A->split_p,
+                                     A->split_t0, A->split_t1, maxv);
     hipLaunchKernelGGL(k_tile_sentinel, dim3(1), dim3(1), 0, s, np, ntiles, A->blk_ptr,
-                       A->panel_val, A->tile_p, A->tile_b, A->tile_v);
-    if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess)
-        status = hip_fail(e, "filling the tile schedule");
+                       A->panel_val, A->tile_p, A->tile_b, A->tile_v, A->tile_f);
+    int hmax = 0;
+    if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess ||
+        (e = hipMemcpy(&hmax, maxv, 4, hipMemcpyDeviceToHost)) != hipSuccess)
+        return bail(e, "filling the tile schedule");
+    A->max_tile_values = hmax;
     A->ntiles_staged = ntiles;
+    A->nsplit = nsplit;
     cleanup();
-    return status;
+    return SPC5_OK;
 }
 
 // ---------------------------------------------------------------- launch
@@ -474,8 +578,15 @@ static hipError_t launch_stream_g(const spc5_matrix *A, const T *val, const T *x
     }
     const int64_t nwg = (nt + tpw - 1) / tpw;
     hipLaunchKernelGGL((k_spmv_stream<T, R, C, NVG>), dim3((unsigned)nwg), dim3(kWG), 0, s, A->nrows,
-                       A->ncols, nt, tpw, nwg, remap, A->tile_p, A->tile_b, A->tile_v, A->blk_ptr,
-                       A->blk_col, (const typename MaskOf<C>::type *)A->masks, val, x, y);
+                       A->ncols, nt, tpw, nwg, remap, A->tile_p, A->tile_b, A->tile_v, A->tile_f,
+                       A->blk_ptr, A->blk_col, (const typename MaskOf<C>::type *)A->masks, val, x,
+                       y, (T *)A->partial);
+    if (A->nsplit > 0) {
+        const int64_t n = A->nsplit * R;
+        hipLaunchKernelGGL(k_split_fixup<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           A->nsplit, R, A->nrows, A->split_p, A->split_t0, A->split_t1,
+                           (const T *)A->partial, y);
+    }
     return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ STATUS = {0: "SPC5_OK", -1: "SPC5_EINVAL", -2: "SPC5_EBADCSR", -3: "SPC5_ENOMEM"
 EXPORTS = [
     "csr_to_spc5", "spc5_free", "spc5_get_info", "spc5_export", "spc5_set_schedule",
     "spc5_spmv", "spc5_spmv_values", "spc5_spmv_transpose", "spc5_spmv_transpose_values",
-    "spc5_values_grad", "spc5_spmm", "spc5_batch_create", "spc5_batch_free",
+    "spc5_prepare_transpose", "spc5_values_grad", "spc5_spmm", "spc5_batch_create", "spc5_batch_free",
     "spc5_batch_set_operands", "spc5_batch_run", "spc5_batch_spmm", "spc5_plan",
     "spc5_csr_create", "spc5_csr_free", "spc5_csr_spmv",
     "spc5_csr_bytes", "spc5_last_error", "spc5_version",
@@ -45,7 +45,10 @@ class spc5_info(ctypes.Structure):
                 ("kernel", ctypes.c_int32), ("ntiles", ctypes.c_int64),
                 ("max_panel_blocks", ctypes.c_int64),
                 ("fill", ctypes.c_double), ("spmv_bytes", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("transpose_r", ctypes.c_int),
+                ("transpose_c", ctypes.c_int), ("transpose_kernel", ctypes.c_int),
+                ("transpose_pad", ctypes.c_int), ("transpose_bytes", ctypes.c_int64),
+                ("split_panels", ctypes.c_int64)]
 
 
 _lib = None
@@ -71,6 +74,7 @@ def lib():
         L.spc5_spmv_transpose.argtypes = [P, P, P, P]
         L.spc5_spmv_transpose_values.argtypes = [P, P, P, P, P]
         L.spc5_values_grad.argtypes = [P, P, P, P, P]
+        L.spc5_prepare_transpose.argtypes = [P, I, I]
         L.spc5_spmm.argtypes = [P, I, P, P, P]
         L.spc5_batch_create.argtypes = [I, P, ctypes.POINTER(P)]
         L.spc5_batch_free.argtypes = [P]
@@ -229,6 +233,16 @@ class Spc5Matrix:
                                       _dev_ptr(x, inf.dtype, inf.ncols, "x"),
                                       _dev_ptr(y, inf.dtype, inf.nrows, "y"), _stream(stream)))
         return y
+
+    def prepare_transpose(self, r: int = 0, c: int = 0):
+        """Build the transposed-product plan (A^T stored in beta(r,c), 0 = own
+        shape): transposes then run as forward products, without atomics."""
+        _check(lib().spc5_prepare_transpose(self._h, r, c))
+        self.info = self._info()
+
+    @property
+    def has_transpose_plan(self) -> bool:
+        return self.info.transpose_r > 0
 
     def transpose(self, ybar, xbar=None, values=None, stream=None):
         import torch

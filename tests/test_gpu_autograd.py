@@ -37,15 +37,18 @@ def packed_coords(O):
     return r, c
 
 
+@pytest.mark.parametrize("plan", [False, True], ids=["scatter", "plan"])
 @pytest.mark.parametrize("rc", [(1, 8), (2, 4), (4, 4), (3, 5)], ids=str)
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
-def test_autograd_vs_dense_reference(rc, dtype, dev):
+def test_autograd_vs_dense_reference(rc, dtype, plan, dev):
     from paper_2307_14774_amd import spc5
     from paper_2307_14774_amd.autograd import spc5_matvec
     r, c = rc
     A = W.random_sparse(37, 29, 0.2, seed=31)
-    say(f"autograd dense ref beta{rc} {dtype}")
+    say(f"autograd dense ref beta{rc} {dtype} plan={plan}")
     M = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c, dtype)
+    if plan:
+        M.prepare_transpose()
     O = oracle.csr_to_spc5(A.rowptr, A.colidx, A.values, A.ncols, r, c)
     tdt = torch.float64 if dtype == "float64" else torch.float32
     rng = np.random.default_rng(5)
@@ -74,14 +77,16 @@ def test_autograd_vs_dense_reference(rc, dtype, dev):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("rc", [(1, 8), (2, 4)], ids=str)
-def test_autograd_finite_differences_graph(rc, dev):
+@pytest.mark.parametrize("rc,plan", [((1, 8), True), ((2, 4), False)], ids=str)
+def test_autograd_finite_differences_graph(rc, plan, dev):
     from paper_2307_14774_amd import spc5
     from paper_2307_14774_amd.autograd import spc5_matvec
     r, c = rc
-    say(f"autograd FD on the 2^20 Zipf graph beta{rc}")
+    say(f"autograd FD on the 2^20 Zipf graph beta{rc} plan={plan}")
     G = W.zipf_graph(1 << 20, seed=0)
     M = spc5.Spc5Matrix.from_csr(G.rowptr, G.colidx, G.values, G.ncols, r, c, "float32")
+    if plan:
+        M.prepare_transpose()
     O = oracle.csr_to_spc5(G.rowptr, G.colidx, G.values, G.ncols, r, c)
     rng = np.random.default_rng(0)
     theta32 = rng.uniform(-1, 1, O.nnz).astype(np.float32)

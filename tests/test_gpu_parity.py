@@ -209,6 +209,75 @@ def test_csr_kernel(A, dev):
     assert row_error_bound_ok(y, A, A.x, 2.0 ** -53).size == 0
 
 
+def long_panel_matrix(seed):
+    """Short rows with a few very long ones (hub rows: thousands of nonzeros,
+    dense runs and scattered columns), so staged tiles must split panels."""
+    rng = np.random.default_rng(seed)
+    n, m = 2000, 30000
+    rows = []
+    for i in range(n):
+        if i in (0, 7, 513, 1998, 1999):
+            k = int(rng.integers(3000, 9000))
+            cols = np.unique(np.concatenate([np.arange(100, 100 + k // 2),
+                                             rng.choice(m, k // 2, replace=False)]))
+        else:
+            cols = np.unique(rng.choice(m, int(rng.integers(0, 12)), replace=False))
+        rows.append(cols)
+    counts = np.array([len(c) for c in rows])
+    colidx = np.concatenate(rows).astype(np.int32)
+    vals = rng.uniform(-1, 1, colidx.shape[0])
+    x = rng.uniform(-1, 1, m)
+    return W._finish(n, m, counts, colidx, vals, x, "hubs2000")
+
+
+@pytest.mark.parametrize("rc", [(1, 8), (1, 16), (2, 4), (4, 4), (8, 8), (3, 5)],
+                         ids=lambda t: "b%d_%d" % t)
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_split_long_panels(rc, dtype, dev):
+    """Panels longer than a staged tile are cut into pieces on several
+    workgroups and summed by the fixup kernel: exact against the oracle,
+    bit-reproducible, and the automatic choice for every r."""
+    r, c = rc
+    A = long_panel_matrix(27)
+    say(f"split panels beta{rc} {dtype}")
+    S = spc5()
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c, dtype)
+    assert M.kernel == "staged"
+    assert M.info.split_panels > 0
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    x = to_dev(A.x, dev, tdt)
+    y1 = M.spmv(x).cpu().numpy()
+    y2 = M.spmv(x).cpu().numpy()
+    assert np.array_equal(y1, y2)
+    if dtype == "float64":
+        ref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
+        assert oracle.rel_l2(y1, ref) <= 1e-14
+        assert len(row_error_bound_ok(y1, A, A.x, 2.0 ** -53)) == 0
+    else:
+        v32 = A.values.astype(np.float32).astype(np.float64)
+        x32 = A.x.astype(np.float32).astype(np.float64)
+        ref = oracle.csr_spmv(A.rowptr, A.colidx, v32, x32)
+        assert oracle.rel_l2(y1, ref) <= 1e-6
+    # narrower tiles: more pieces, same result within rounding
+    M.set_schedule("staged", 3)
+    y3 = M.spmv(x).cpu().numpy()
+    assert oracle.rel_l2(y3, ref) <= (1e-14 if dtype == "float64" else 1e-6)
+
+
+def test_split_transpose_plan_zipf(dev):
+    """A^T of a Zipf-column graph has very long rows (popular columns): the
+    plan's forward over A^T splits them; compared with the oracle."""
+    A = W.zipf_graph(1 << 14, seed=3)
+    S = spc5()
+    say("transpose plan zipf 2^14")
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 1, 8)
+    M.prepare_transpose()
+    w = np.random.default_rng(4).uniform(-1, 1, A.nrows)
+    xb = M.transpose(to_dev(w, dev)).cpu().numpy()
+    ref = oracle.csr_spmv_t(A.rowptr, A.colidx, A.values, w, A.ncols)
+    assert oracle.rel_l2(xb, ref) <= 1e-14
+
+
 # ------------------------------------------------------------ backward
 
 @pytest.mark.parametrize("A", CASES[4:], ids=lambda a: a.name)
@@ -230,13 +299,54 @@ def test_transpose(A, rc, dev):
     assert np.all(np.abs(xb - ref) <= g * absum)
 
 
+@pytest.mark.parametrize("A", CASES, ids=lambda a: a.name)
+@pytest.mark.parametrize("rc,trc", [((1, 8), (0, 0)), ((2, 4), (0, 0)), ((4, 4), (0, 0)),
+                                    ((3, 5), (4, 4)), ((8, 16), (1, 8)), ((4, 4), (2, 8))],
+                         ids=lambda t: "b%d_%d" % t)
+def test_transpose_plan(A, rc, trc, dev):
+    """x_bar = A^T y_bar through the stored A^T (forward kernel, no atomics):
+    against the oracle's CSR transpose, reproducible bit for bit, and with
+    caller values theta in A's packed order."""
+    r, c = rc
+    S = spc5()
+    say(f"transpose plan {A.name} beta{rc} -> A^T beta{trc}")
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+    M.prepare_transpose(*trc)
+    assert M.has_transpose_plan
+    assert (M.info.transpose_r, M.info.transpose_c) == (trc[0] or r, trc[1] or c)
+    M.prepare_transpose(*trc)          # same shape again: no-op
+    rng = np.random.default_rng(26)
+    w = rng.uniform(-1, 1, A.nrows)
+    wd = to_dev(w, dev)
+    xb = M.transpose(wd).cpu().numpy()
+    ref = oracle.csr_spmv_t(A.rowptr, A.colidx, A.values, w, A.ncols)
+    assert oracle.rel_l2(xb, ref) <= 1e-14
+    absum = oracle.csr_spmv_t(A.rowptr, A.colidx, np.abs(A.values), np.abs(w), A.ncols)
+    ncol = np.bincount(A.colidx, minlength=A.ncols).astype(np.float64)
+    g = (ncol + 1) * 2.0 ** -52 / (1 - (ncol + 1) * 2.0 ** -52)
+    assert np.all(np.abs(xb - ref) <= g * absum)
+    assert np.array_equal(M.transpose(wd).cpu().numpy().view(np.uint64), xb.view(np.uint64))
+    # caller values theta (packed order of A)
+    O = oracle.csr_to_spc5(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+    theta = rng.uniform(-1, 1, O.nnz)
+    Ot = oracle.Spc5(**{**O.__dict__, "values": theta})
+    rp, ci, vals = oracle.spc5_to_csr(Ot)
+    xt = M.transpose(wd, values=to_dev(theta, dev)).cpu().numpy()
+    assert oracle.rel_l2(xt, oracle.csr_spmv_t(rp, ci, vals, w, A.ncols)) <= 1e-14
+    # the matrix's own values again after a caller-values call
+    assert np.array_equal(M.transpose(wd).cpu().numpy().view(np.uint64), xb.view(np.uint64))
+
+
+@pytest.mark.parametrize("plan", [False, True], ids=["scatter", "plan"])
 @pytest.mark.parametrize("rc", MAIN + [(8, 8), (3, 5)], ids=lambda t: "b%d_%d" % t)
-def test_transpose_unit_rows_and_integers(rc, dev):
+def test_transpose_unit_rows_and_integers(rc, plan, dev):
     r, c = rc
     A = W.random_sparse(90, 70, 0.1, seed=17, integer=True)
     S = spc5()
     M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c)
-    say(f"transpose exact beta{rc}")
+    if plan:
+        M.prepare_transpose()
+    say(f"transpose exact beta{rc} plan={plan}")
     for i in [0, 3, 44, 89]:
         e = np.zeros(A.nrows)
         e[i] = 1.0
