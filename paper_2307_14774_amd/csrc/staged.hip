@@ -37,8 +37,6 @@
 
 namespace spc5 {
 
-typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-
 constexpr int kWG = 256;   // threads per workgroup (4 wavefronts)
 
 template <typename T, int R, int C, int NVG = 4>
@@ -121,9 +119,11 @@ __device__ __forceinline__ unsigned lds_block_union(const uint8_t *sm, int t) {
 }
 
 // A contiguous byte range of global memory, as 16-byte vectors from an
-// aligned base.
+// aligned base, addressed through a raw buffer descriptor whose record count
+// is the range's length: vector indices past the range read zeros, so the
+// staging loads need no clamping.
 struct Range16 {
-    const v4u *src;
+    Buf buf;
     int n;       // vectors
     int skew;    // bytes from the aligned base to the first wanted byte
 };
@@ -131,36 +131,18 @@ struct Range16 {
 __device__ __forceinline__ Range16 range16(const void *base, int64_t byte0, int64_t byte1) {
     const int64_t a0 = byte0 & ~(int64_t)15;
     Range16 r;
-    r.src = (const v4u *)((const char *)base + a0);
     r.n = byte1 > byte0 ? (int)((byte1 - a0 + 15) >> 4) : 0;
     r.skew = (int)(byte0 - a0);
+    r.buf = make_buf((const char *)base + a0, (int64_t)r.n * 16);
     return r;
 }
 
-// Register stage of up to NVMAX vectors per thread.  issue(): G unconditional
-// loads (indices clamped into the range), G the smallest power of two (or
-// NVMAX) covering the range, so the loads are straight-line code and all in
-// flight together; commit(): the matching LDS stores.
+// Register stage of up to NVMAX vectors per thread and the matching LDS
+// stores.
 template <int NVMAX>
 struct RegStage {
     v4u r[NVMAX];
 
-    template <int G>
-    __device__ __forceinline__ void issue_g(const Range16 &q) {
-        const int th = threadIdx.x;
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int v = th + kWG * g;
-            r[g] = q.src[v < q.n ? v : q.n - 1];
-        }
-    }
-    __device__ __forceinline__ void issue(const Range16 &q) {
-        if (q.n <= 0) return;
-        if (q.n <= kWG) issue_g<1>(q);
-        else if (NVMAX >= 2 && q.n <= 2 * kWG) issue_g<(NVMAX >= 2 ? 2 : 1)>(q);
-        else if (NVMAX >= 4 && q.n <= 4 * kWG) issue_g<(NVMAX >= 4 ? 4 : 1)>(q);
-        else issue_g<NVMAX>(q);
-    }
     __device__ __forceinline__ void commit(v4u *dst, const Range16 &q) const {
         const int th = threadIdx.x;
 #pragma unroll
@@ -180,9 +162,10 @@ struct TileStage {
     RegStage<Cfg::NC> rc;
     RegStage<Cfg::NP> rp;
 
-    // All NV + NM + NC + NP loads, unconditionally (indices clamped): a fixed
-    // count keeps the compiler's in-order load counters exact, so waiting for
-    // later loads of the current tile never waits for this prefetch.
+    // All NV + NM + NC + NP loads, unconditionally (vectors past a range read
+    // zeros): a fixed count keeps the compiler's in-order load counters
+    // exact, so waiting for later loads of the current tile never waits for
+    // this prefetch.
     __device__ __forceinline__ void issue(int p0, int p1, int b0, int b1, int v0, int v1,
                                           const T *val, const void *masks, const int32_t *blk_col,
                                           const int32_t *blk_ptr) {
@@ -197,17 +180,13 @@ struct TileStage {
     }
     template <int N>
     __device__ __forceinline__ static void fixed(RegStage<N> &st, const Range16 &q) {
-        const int th = threadIdx.x;
-        const int nmax = q.n > 0 ? q.n - 1 : 0;
+        const uint32_t th16 = (uint32_t)threadIdx.x * 16u;
 #pragma unroll
-        for (int g = 0; g < N; ++g) {
-            const int v = th + kWG * g;
-            st.r[g] = q.src[v < nmax ? v : nmax];
-        }
+        for (int g = 0; g < N; ++g) st.r[g] = buf_load16(q.buf, th16 + (uint32_t)(kWG * 16 * g));
     }
 };
 
-template <typename T, int R, int C, int NVG>
+template <typename T, int R, int C, int NVG, bool SPARSE>
 __global__ __launch_bounds__(kWG) void k_spmv_stream(
     int64_t nrows, int64_t ncols, int64_t ntiles, int tiles_per_wg, int64_t nwg, int remap,
     const int32_t *__restrict__ tile_p, const int32_t *__restrict__ tile_b,
@@ -226,10 +205,12 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
     __shared__ T s_x[BT * C];
     __shared__ int s_boff[BT];
     __shared__ int s_wsum[kWG / kWave];
+    __shared__ T s_zero[1];
 
     const int th = threadIdx.x;
     const int lane = lane_id();
     const int wv = th / kWave;
+    if (th == 0) s_zero[0] = T(0);   // published by the first tile's barrier
     const int64_t g = remap ? xcd_remap(blockIdx.x, nwg) : (int64_t)blockIdx.x;
     const int64_t t_begin = g * tiles_per_wg;
     const int64_t t_end = min(t_begin + tiles_per_wg, ntiles);
@@ -317,7 +298,12 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
         // a piece tile holds only part of its panel's blocks: clamp
         const int bs = live ? max(sbp[pl], b0) - b0 : 0;
         const int be = live ? min(sbp[pl + 1], b1) - b0 : 0;
-        T acc = T(0);
+        // Masked-off (block, bit) pairs read a zero from s_zero for both
+        // operands, so the FMA needs no select: 0*0 leaves the sum unchanged
+        // and a non-finite x of another row's column is never touched.
+        T acc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] = T(0);
         for (int b = bs + sub; b < be; b += U * S) {
             unsigned m[U];
             int j[U], tt[U];
@@ -330,25 +316,50 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
                 m[u] = ok ? m[u] : 0u;
                 j[u] = s_boff[tt[u]] + pre;
             }
+            if constexpr (SPARSE) {
+                // low fill: one step per set bit, the wave running as many
+                // steps as its fullest row-block has bits
+                T a = acc[0];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+                for (int u = 0; u < U; ++u) {
+                    unsigned mm = m[u];
+                    int jj = j[u];
+                    const T *xb = s_x + tt[u] * C;
+                    while (__ballot(mm != 0u)) {
+                        const bool on = mm != 0u;
+                        const T *pv = on ? sval + jj : s_zero;
+                        const T *px = on ? xb + (__ffs(mm) - 1) : s_zero;
+                        a = fma(*pv, *px, a);
+                        ++jj;
+                        mm &= mm - 1u;
+                    }
+                }
+                acc[0] = a;
+            } else {
+                // high fill: every bit, branch-free; a bit's value index is
+                // the row's first value plus the popcount of the lower bits
 #pragma unroll
-                for (int k = 0; k < C; ++k) {
-                    const bool on = (m[u] >> k) & 1u;
-                    const T v = sval[on ? j[u] : 0];
-                    const T xv = s_x[tt[u] * C + k];
-                    const T r = fma(v, xv, acc);
-                    acc = on ? r : acc;
-                    j[u] += on ? 1 : 0;
+                for (int u = 0; u < U; ++u) {
+#pragma unroll
+                    for (int k = 0; k < C; ++k) {
+                        const bool on = (m[u] >> k) & 1u;
+                        const int jk = k ? j[u] + __popc(m[u] & ((1u << k) - 1u)) : j[u];
+                        const T *pv = on ? sval + jk : s_zero;
+                        const T *px = on ? s_x + tt[u] * C + k : s_zero;
+                        acc[u] = fma(*pv, *px, acc[u]);
+                    }
                 }
             }
         }
+        T accs = acc[0];
+#pragma unroll
+        for (int u = 1; u < U; ++u) accs += acc[u];
         // 5. sub-lanes of a row are R apart inside one wavefront
-        for (int d = R; d < lps; d <<= 1) acc += __shfl_xor(acc, d);
+        for (int d = R; d < lps; d <<= 1) accs += __shfl_xor(accs, d);
         if (live && sub == 0) {
             const int64_t row = (int64_t)(p0 + pl) * R + i;
-            if (f0) partial[t * R + i] = acc;     // summed by k_split_fixup
-            else if (row < nrows) y[row] = acc;
+            if (f0) partial[t * R + i] = accs;    // summed by k_split_fixup
+            else if (row < nrows) y[row] = accs;
         }
         f0 = g0; p0 = q0; p1 = q1; b0 = c0; b1 = c1; v0 = w0; v1 = w1;
     }
@@ -565,7 +576,7 @@ int build_staged_schedule(spc5_matrix *A, int ppw_req) {
 
 // ---------------------------------------------------------------- launch
 
-template <typename T, int R, int C, int NVG>
+template <typename T, int R, int C, int NVG, bool SPARSE>
 static hipError_t launch_stream_g(const spc5_matrix *A, const T *val, const T *x, T *y,
                                   hipStream_t s, int remap) {
     const int64_t nt = A->ntiles_staged;
@@ -577,7 +588,7 @@ static hipError_t launch_stream_g(const spc5_matrix *A, const T *val, const T *x
         tpw = e ? std::max(1, atoi(e)) : 4;
     }
     const int64_t nwg = (nt + tpw - 1) / tpw;
-    hipLaunchKernelGGL((k_spmv_stream<T, R, C, NVG>), dim3((unsigned)nwg), dim3(kWG), 0, s, A->nrows,
+    hipLaunchKernelGGL((k_spmv_stream<T, R, C, NVG, SPARSE>), dim3((unsigned)nwg), dim3(kWG), 0, s, A->nrows,
                        A->ncols, nt, tpw, nwg, remap, A->tile_p, A->tile_b, A->tile_v, A->tile_f,
                        A->blk_ptr, A->blk_col, (const typename MaskOf<C>::type *)A->masks, val, x,
                        y, (T *)A->partial);
@@ -590,14 +601,33 @@ static hipError_t launch_stream_g(const spc5_matrix *A, const T *val, const T *x
     return hipGetLastError();
 }
 
+// The rows phase loops over set bits only when a row-block holds fewer than
+// c/2 nonzeros on average.
+static bool sparse_rows(const spc5_matrix *A) {
+    static int mode = -2;
+    if (mode == -2) {
+        const char *e = getenv("SPC5_ROWS_MODE");
+        mode = !e ? -1 : (e[0] == 's' ? 1 : (e[0] == 'd' ? 0 : -1));
+    }
+    if (mode >= 0) return mode == 1;
+    return A->nblocks > 0 && 2.0 * (double)A->nnz < (double)A->nblocks * A->r * A->c;
+}
+
 // LDS value buffer sized to the largest tile of the matrix: 4, 8 or 16 KiB.
+template <typename T, int R, int C, bool SPARSE>
+static hipError_t launch_stream_s(const spc5_matrix *A, const T *val, const T *x, T *y,
+                                  hipStream_t s, int remap) {
+    const int64_t need = (int64_t)A->max_tile_values * (int64_t)sizeof(T) + 16;
+    if (need <= 4096) return launch_stream_g<T, R, C, 1, SPARSE>(A, val, x, y, s, remap);
+    if (need <= 8192) return launch_stream_g<T, R, C, 2, SPARSE>(A, val, x, y, s, remap);
+    return launch_stream_g<T, R, C, 4, SPARSE>(A, val, x, y, s, remap);
+}
+
 template <typename T, int R, int C>
 static hipError_t launch_stream(const spc5_matrix *A, const T *val, const T *x, T *y,
                                 hipStream_t s, int remap) {
-    const int64_t need = (int64_t)A->max_tile_values * (int64_t)sizeof(T) + 16;
-    if (need <= 4096) return launch_stream_g<T, R, C, 1>(A, val, x, y, s, remap);
-    if (need <= 8192) return launch_stream_g<T, R, C, 2>(A, val, x, y, s, remap);
-    return launch_stream_g<T, R, C, 4>(A, val, x, y, s, remap);
+    return sparse_rows(A) ? launch_stream_s<T, R, C, true>(A, val, x, y, s, remap)
+                          : launch_stream_s<T, R, C, false>(A, val, x, y, s, remap);
 }
 
 template <typename T>

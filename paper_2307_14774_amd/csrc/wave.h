@@ -60,6 +60,13 @@ template <> __device__ __forceinline__ float buf_load<float>(const Buf &b, uint3
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)off, 0, 0));
 }
 
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+// 16-byte raw buffer load (zeros when out of the descriptor's range).
+__device__ __forceinline__ v4u buf_load16(const Buf &b, uint32_t off) {
+    return __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)off, 0, 0));
+}
+
 template <int C> struct MaskOf { using type = uint8_t; };
 template <> struct MaskOf<16> { using type = uint16_t; };
 
