@@ -47,12 +47,10 @@ bool x_fits_buffer(const spc5_matrix *A) {
 }
 
 int auto_kernel(const spc5_matrix *A) {
-    // Staged for r > 1 (the r rows of a block share its x window).  For
-    // beta(1,c) the sweep kernel is faster, unless a panel is longer than a
-    // tile: only the staged schedule splits such panels across workgroups.
-    // The staged and row kernels address x through a 2 GiB buffer range.
+    // The staged kernel (value mode for beta(1,c)) whenever its 2 GiB buffer
+    // range covers x; the sweep kernel otherwise.
     if (!A->staged_ok || !x_fits_buffer(A)) return SPC5_KERNEL_SWEEP;
-    return A->r > 1 || A->nsplit > 0 ? SPC5_KERNEL_STAGED : SPC5_KERNEL_SWEEP;
+    return SPC5_KERNEL_STAGED;
 }
 
 int finish_matrix(spc5_matrix *A) {

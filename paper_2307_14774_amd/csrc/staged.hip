@@ -47,7 +47,10 @@ struct StreamCfg {
     static constexpr int VBYTES = 4096 * NVG;
     static constexpr int VT = (16384 - 16) / (int)sizeof(T);           // schedule cap
     static constexpr int BT0 = 8192 / (C * (int)sizeof(T));
-    static constexpr int BT = BT0 < 256 ? BT0 : 256;                   // blocks per tile
+    // blocks per tile: bounded by the x windows in LDS (C per block); beta(1,c)
+    // keeps no windows (value mode) and gives each thread BPT blocks
+    static constexpr int BPT = R == 1 ? 4 : 1;
+    static constexpr int BT = R == 1 ? kWG * BPT : (BT0 < 256 ? BT0 : 256);
     static constexpr int PPW = kWG / R;                                // panels per tile
     static constexpr int VVEC = VBYTES / 16;
     static constexpr int MVEC = (BT * R * MB + 30) / 16;
@@ -65,7 +68,7 @@ void staged_caps(const spc5_matrix *A, int *vt, int *bt, int *ppw) {
     const int sz = A->dtype == SPC5_F64 ? 8 : 4;
     const int cm = A->c <= 4 ? 4 : (A->c <= 8 ? 8 : 16);
     *vt = (16384 - 16) / sz;
-    *bt = std::min(256, 8192 / (cm * sz));
+    *bt = A->r == 1 ? 4 * kWG : std::min(256, 8192 / (cm * sz));
     *ppw = kWG / A->r;
 }
 
@@ -186,6 +189,89 @@ struct TileStage {
     }
 };
 
+// Rows phase of one staged tile: thread = (panel pl, sub-lane, row i) with S
+// sub-lanes per row (np*R*S <= 256 and S*R <= 64, so the butterfly stays in
+// a wavefront).  Returns the row sum on every sub-lane; `lead` marks the
+// sub-lane that stores it.
+template <typename T, int R, int C, int U, bool SPARSE>
+__device__ __forceinline__ T tile_rows(int np, int b0, int b1, const int *sbp, const uint8_t *smb,
+                                       const int *s_boff, const T *sval, const T *s_x,
+                                       const T *s_zero, int &pl_out, int &i_out, bool &lead) {
+    const int th = threadIdx.x;
+    int lgS = 0;
+    if ((R & (R - 1)) == 0)
+        while (np * R * (2 << lgS) <= kWG && R * (2 << lgS) <= kWave) ++lgS;
+    const int S = 1 << lgS;
+    const int lps = S * R;
+    const int pl = th / lps, sub = (th / R) & (S - 1), i = th % R;
+    const bool live = pl < np;
+    // a piece tile holds only part of its panel's blocks: clamp
+    const int bs = live ? max(sbp[pl], b0) - b0 : 0;
+    const int be = live ? min(sbp[pl + 1], b1) - b0 : 0;
+    // Masked-off (block, bit) pairs read a zero from s_zero for both
+    // operands, so the FMA needs no select: 0*0 leaves the sum unchanged
+    // and a non-finite x of another row's column is never touched.
+    T acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = T(0);
+    for (int b = bs + sub; b < be; b += U * S) {
+        unsigned m[U];
+        int j[U], tt[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = b + u * S < be;
+            tt[u] = ok ? b + u * S : b;
+            int pre, tot;
+            lds_block_masks<R, C>(smb, tt[u], i, m[u], pre, tot);
+            m[u] = ok ? m[u] : 0u;
+            j[u] = s_boff[tt[u]] + pre;
+        }
+        if constexpr (SPARSE) {
+            // low fill: one step per set bit, the wave running as many
+            // steps as its fullest row-block has bits
+            T a = acc[0];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                unsigned mm = m[u];
+                int jj = j[u];
+                const T *xb = s_x + tt[u] * C;
+                while (__ballot(mm != 0u)) {
+                    const bool on = mm != 0u;
+                    const T *pv = on ? sval + jj : s_zero;
+                    const T *px = on ? xb + (__ffs(mm) - 1) : s_zero;
+                    a = fma(*pv, *px, a);
+                    ++jj;
+                    mm &= mm - 1u;
+                }
+            }
+            acc[0] = a;
+        } else {
+            // high fill: every bit, branch-free; a bit's value index is the
+            // row's first value plus the popcount of the lower bits
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    const bool on = (m[u] >> k) & 1u;
+                    const int jk = k ? j[u] + __popc(m[u] & ((1u << k) - 1u)) : j[u];
+                    const T *pv = on ? sval + jk : s_zero;
+                    const T *px = on ? s_x + tt[u] * C + k : s_zero;
+                    acc[u] = fma(*pv, *px, acc[u]);
+                }
+            }
+        }
+    }
+    T accs = acc[0];
+#pragma unroll
+    for (int u = 1; u < U; ++u) accs += acc[u];
+    // sub-lanes of a row are R apart inside one wavefront
+    for (int d = R; d < lps; d <<= 1) accs += __shfl_xor(accs, d);
+    pl_out = pl;
+    i_out = i;
+    lead = live && sub == 0;
+    return accs;
+}
+
 template <typename T, int R, int C, int NVG, bool SPARSE>
 __global__ __launch_bounds__(kWG) void k_spmv_stream(
     int64_t nrows, int64_t ncols, int64_t ntiles, int tiles_per_wg, int64_t nwg, int remap,
@@ -259,10 +345,14 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
             xw[k] = buf_load<T>(xbuf, ((un >> k) & 1u) ? (uint32_t)(col0 + k) * (uint32_t)sizeof(T)
                                                        : kOOB);
         // ... then the next tile's staging loads, so both are in flight
-        // together and waiting for the gathers does not wait for them.  On the
-        // last tile the current tile is re-requested (cache hits): keeping the
-        // issue unconditional keeps the load counters exact on every path.
+        // together and waiting for the gathers does not wait for them (the
+        // scheduling barriers keep the compiler from reordering the groups).
+        // On the last tile the current tile is re-requested (cache hits):
+        // keeping the issue unconditional keeps the load counters exact on
+        // every path.
+        __builtin_amdgcn_sched_barrier(0);
         st.issue(q0, q1, c0, c1, w0, w1, val, masks, blk_col, blk_ptr);
+        __builtin_amdgcn_sched_barrier(0);
 
         // 2. block value offsets (workgroup exclusive scan of block popcounts)
         int cnt = 0;
@@ -286,80 +376,167 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
         }
         __syncthreads();
 
-        // 4. rows: thread = (panel, sub-lane, row); S sub-lanes per row with
-        //    np*R*S <= 256 and S*R <= 64 (the butterfly stays in a wavefront)
-        int lgS = 0;
-        if ((R & (R - 1)) == 0)
-            while (np * R * (2 << lgS) <= kWG && R * (2 << lgS) <= kWave) ++lgS;
-        const int S = 1 << lgS;
-        const int lps = S * R;
-        const int pl = th / lps, sub = (th / R) & (S - 1), i = th % R;
-        const bool live = pl < np;
-        // a piece tile holds only part of its panel's blocks: clamp
-        const int bs = live ? max(sbp[pl], b0) - b0 : 0;
-        const int be = live ? min(sbp[pl + 1], b1) - b0 : 0;
-        // Masked-off (block, bit) pairs read a zero from s_zero for both
-        // operands, so the FMA needs no select: 0*0 leaves the sum unchanged
-        // and a non-finite x of another row's column is never touched.
-        T acc[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] = T(0);
-        for (int b = bs + sub; b < be; b += U * S) {
-            unsigned m[U];
-            int j[U], tt[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool ok = b + u * S < be;
-                tt[u] = ok ? b + u * S : b;
-                int pre, tot;
-                lds_block_masks<R, C>(smb, tt[u], i, m[u], pre, tot);
-                m[u] = ok ? m[u] : 0u;
-                j[u] = s_boff[tt[u]] + pre;
-            }
-            if constexpr (SPARSE) {
-                // low fill: one step per set bit, the wave running as many
-                // steps as its fullest row-block has bits
-                T a = acc[0];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    unsigned mm = m[u];
-                    int jj = j[u];
-                    const T *xb = s_x + tt[u] * C;
-                    while (__ballot(mm != 0u)) {
-                        const bool on = mm != 0u;
-                        const T *pv = on ? sval + jj : s_zero;
-                        const T *px = on ? xb + (__ffs(mm) - 1) : s_zero;
-                        a = fma(*pv, *px, a);
-                        ++jj;
-                        mm &= mm - 1u;
-                    }
-                }
-                acc[0] = a;
-            } else {
-                // high fill: every bit, branch-free; a bit's value index is
-                // the row's first value plus the popcount of the lower bits
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-#pragma unroll
-                    for (int k = 0; k < C; ++k) {
-                        const bool on = (m[u] >> k) & 1u;
-                        const int jk = k ? j[u] + __popc(m[u] & ((1u << k) - 1u)) : j[u];
-                        const T *pv = on ? sval + jk : s_zero;
-                        const T *px = on ? s_x + tt[u] * C + k : s_zero;
-                        acc[u] = fma(*pv, *px, acc[u]);
-                    }
-                }
-            }
-        }
-        T accs = acc[0];
-#pragma unroll
-        for (int u = 1; u < U; ++u) accs += acc[u];
-        // 5. sub-lanes of a row are R apart inside one wavefront
-        for (int d = R; d < lps; d <<= 1) accs += __shfl_xor(accs, d);
-        if (live && sub == 0) {
+        // 4. rows and 5. butterfly, then one store per row
+        int pl, i;
+        bool lead;
+        const T accs = tile_rows<T, R, C, U, SPARSE>(np, b0, b1, sbp, smb, s_boff, sval, s_x,
+                                                     s_zero, pl, i, lead);
+        if (lead) {
             const int64_t row = (int64_t)(p0 + pl) * R + i;
             if (f0) partial[t * R + i] = accs;    // summed by k_split_fixup
             else if (row < nrows) y[row] = accs;
+        }
+        f0 = g0; p0 = q0; p1 = q1; b0 = c0; b1 = c1; v0 = w0; v1 = w1;
+    }
+}
+
+// ---------------------------------------------------------------- value mode
+
+// beta(1,c) in VALUE MODE: with one row per block there is no x window to
+// share between rows, and at low fill most of a block's c columns are empty,
+// so the x loads go per nonzero instead of per block column.  Per tile: the
+// block popcount scan gives every block its first value; one thread per block
+// decodes its values' columns (anchor + position of each set bit) into LDS;
+// every thread then gathers x for a fixed number of value slots (unconditional
+// buffer loads, out of range past the tile), multiplies in place, and the
+// rows -- contiguous value ranges for r = 1 -- are summed by S sub-lanes and
+// a butterfly.  The staging, prefetch and piece tiles are those of the
+// staged kernel.
+template <typename T, int C, int NVG>
+__global__ __launch_bounds__(kWG) void k_spmv_vstream(
+    int64_t nrows, int64_t ncols, int64_t ntiles, int tiles_per_wg, int64_t nwg, int remap,
+    const int32_t *__restrict__ tile_p, const int32_t *__restrict__ tile_b,
+    const int32_t *__restrict__ tile_v, const int32_t *__restrict__ tile_f,
+    const int32_t *__restrict__ blk_ptr,
+    const int32_t *__restrict__ blk_col, const typename MaskOf<C>::type *__restrict__ masks,
+    const T *__restrict__ val, const T *__restrict__ x, T *__restrict__ y,
+    T *__restrict__ partial)
+{
+    using Cfg = StreamCfg<T, 1, C, NVG>;
+    using MT = typename MaskOf<C>::type;
+    constexpr int BT = Cfg::BT;
+    constexpr int VCAP = Cfg::VVEC * 16 / (int)sizeof(T);    // value slots of a tile
+    constexpr int NX = (VCAP + kWG - 1) / kWG;               // value slots per thread
+    __shared__ v4u s_val[Cfg::VVEC];
+    __shared__ v4u s_mask[Cfg::MVEC];
+    __shared__ v4u s_col[Cfg::CVEC];
+    __shared__ v4u s_bp[Cfg::PVEC];
+    __shared__ int s_vcol[VCAP];
+    __shared__ int s_boff[BT + 1];
+    __shared__ int s_wsum[kWG / kWave];
+
+    const int th = threadIdx.x;
+    const int lane = lane_id();
+    const int wv = th / kWave;
+    const int64_t g = remap ? xcd_remap(blockIdx.x, nwg) : (int64_t)blockIdx.x;
+    const int64_t t_begin = g * tiles_per_wg;
+    const int64_t t_end = min(t_begin + tiles_per_wg, ntiles);
+    const Buf xbuf = make_buf(x, ncols * (int64_t)sizeof(T));
+
+    int f0 = tile_f[t_begin];
+    int p0 = tile_p[t_begin], p1 = f0 ? p0 + 1 : tile_p[t_begin + 1];
+    int b0 = tile_b[t_begin], b1 = tile_b[t_begin + 1];
+    int v0 = tile_v[t_begin], v1 = tile_v[t_begin + 1];
+    TileStage<T, 1, C, NVG> st;
+    st.issue(p0, p1, b0, b1, v0, v1, val, masks, blk_col, blk_ptr);
+
+    for (int64_t t = t_begin; t < t_end; ++t) {
+        const bool more = t + 1 < t_end;
+        const int64_t tn = more ? t + 1 : t;
+        const int g0 = tile_f[tn];
+        const int q0 = tile_p[tn], q1 = g0 ? q0 + 1 : tile_p[tn + 1];
+        const int c0 = tile_b[tn], c1 = tile_b[tn + 1];
+        const int w0 = tile_v[tn], w1 = tile_v[tn + 1];
+
+        __syncthreads();
+        st.rm.commit(s_mask, st.qm);
+        st.rc.commit(s_col, st.qc);
+        st.rp.commit(s_bp, st.qp);
+        st.rv.commit(s_val, st.qv);
+        const int skv = st.qv.skew, skm = st.qm.skew, skc = st.qc.skew, skp = st.qp.skew;
+        __syncthreads();
+        const MT *smk = (const MT *)((const uint8_t *)s_mask + skm);
+        const int *scol = (const int *)((const uint8_t *)s_col + skc);
+        const int *sbp = (const int *)((const uint8_t *)s_bp + skp);
+        T *sval = (T *)((uint8_t *)s_val + skv);
+        const int np = p1 - p0;
+        const int nbt = b1 - b0;
+        const int nv = v1 - v0;
+
+        // first value of every block (workgroup scan of popcounts); thread th
+        // owns blocks BPT*th .. BPT*th+BPT-1
+        constexpr int BPT = Cfg::BPT;
+        unsigned m[BPT];
+        int cnt[BPT], own = 0;
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int tb = BPT * th + q;
+            m[q] = tb < nbt ? (unsigned)smk[tb] : 0u;
+            cnt[q] = __popc(m[q]);
+            own += cnt[q];
+        }
+        const int incl = wave_incl_scan(own);
+        if (lane == kWave - 1) s_wsum[wv] = incl;
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int w2 = 0; w2 < kWG / kWave; ++w2) {
+            before += w2 < wv ? s_wsum[w2] : 0;
+            total += s_wsum[w2];
+        }
+        int boff = before + incl - own;
+        if (th == 0) s_boff[nbt] = total;
+        // column of every value: anchor + position of each set bit
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int tb = BPT * th + q;
+            if (tb < nbt) {
+                s_boff[tb] = boff;
+                const int c0b = scol[tb];
+                unsigned mm = m[q];
+                int v = boff;
+                while (mm) {
+                    s_vcol[v++] = c0b + __ffs(mm) - 1;
+                    mm &= mm - 1u;
+                }
+            }
+            boff += cnt[q];
+        }
+        __syncthreads();
+
+        // one x load per value slot, then the next tile's staging loads
+        T xg[NX];
+#pragma unroll
+        for (int k = 0; k < NX; ++k) {
+            const int v = th + kWG * k;
+            xg[k] = buf_load<T>(xbuf, v < nv ? (uint32_t)s_vcol[v] * (uint32_t)sizeof(T) : kOOB);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        st.issue(q0, q1, c0, c1, w0, w1, val, masks, blk_col, blk_ptr);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < NX; ++k) {
+            const int v = th + kWG * k;
+            if (v < nv) sval[v] = sval[v] * xg[k];
+        }
+        __syncthreads();
+
+        // rows: S sub-lanes per row over its contiguous products
+        int lgS = 0;
+        while (np * (2 << lgS) <= kWG && (2 << lgS) <= kWave) ++lgS;
+        const int S = 1 << lgS;
+        const int pl = th >> lgS, sub = th & (S - 1);
+        const bool live = pl < np;
+        const int bs = live ? max(sbp[pl], b0) - b0 : 0;
+        const int be = live ? min(sbp[pl + 1], b1) - b0 : 0;
+        const int vs = s_boff[bs], ve = s_boff[be];
+        T acc = T(0);
+        for (int v = vs + sub; v < ve; v += S) acc += sval[v];
+        for (int d = 1; d < S; d <<= 1) acc += __shfl_xor(acc, d);
+        if (live && sub == 0) {
+            const int64_t row = (int64_t)(p0 + pl);
+            if (f0) partial[t] = acc;              // summed by k_split_fixup
+            else if (row < nrows) y[row] = acc;
         }
         f0 = g0; p0 = q0; p1 = q1; b0 = c0; b1 = c1; v0 = w0; v1 = w1;
     }
@@ -491,6 +668,10 @@ int build_staged_schedule(spc5_matrix *A, int ppw_req) {
     int vt, bt, ppw;
     staged_caps(A, &vt, &bt, &ppw);
     if (ppw_req > 0) ppw = std::min(ppw, ppw_req);
+    // small matrices: narrower tiles, so that there are about 2048 of them
+    // to spread over the 256 compute units
+    bt = (int)std::min<int64_t>(bt, std::max<int64_t>(32, A->nblocks / 2048));
+    vt = (int)std::min<int64_t>(vt, std::max<int64_t>(256, A->nnz / 2048));
     A->sppt = ppw;
     A->max_tile_values = 0;
     if (A->npanels == 0) return SPC5_OK;
@@ -581,17 +762,29 @@ static hipError_t launch_stream_g(const spc5_matrix *A, const T *val, const T *x
                                   hipStream_t s, int remap) {
     const int64_t nt = A->ntiles_staged;
     if (nt == 0) return hipSuccess;
-    // consecutive tiles per workgroup (the next one is prefetched)
-    static int tpw = -1;
-    if (tpw < 0) {
+    // consecutive tiles per workgroup, the next one always prefetched: 8 on
+    // very large matrices (fewer workgroup start-ups), fewer on smaller ones
+    // (enough workgroups to spread); SPC5_TILES_PER_WG overrides
+    static int tpw_env = -2;
+    if (tpw_env == -2) {
         const char *e = getenv("SPC5_TILES_PER_WG");
-        tpw = e ? std::max(1, atoi(e)) : 4;
+        tpw_env = e ? std::max(1, atoi(e)) : -1;
     }
+    const int tpw = tpw_env > 0 ? tpw_env
+                                : (nt >= 32768 ? 8 : nt >= 8192 ? 4 : nt >= 4096 ? 2 : 1);
     const int64_t nwg = (nt + tpw - 1) / tpw;
-    hipLaunchKernelGGL((k_spmv_stream<T, R, C, NVG, SPARSE>), dim3((unsigned)nwg), dim3(kWG), 0, s, A->nrows,
-                       A->ncols, nt, tpw, nwg, remap, A->tile_p, A->tile_b, A->tile_v, A->tile_f,
-                       A->blk_ptr, A->blk_col, (const typename MaskOf<C>::type *)A->masks, val, x,
-                       y, (T *)A->partial);
+    if constexpr (R == 1)
+        hipLaunchKernelGGL((k_spmv_vstream<T, C, NVG>), dim3((unsigned)nwg), dim3(kWG), 0, s,
+                           A->nrows, A->ncols, nt, tpw, nwg, remap, A->tile_p, A->tile_b,
+                           A->tile_v, A->tile_f, A->blk_ptr, A->blk_col,
+                           (const typename MaskOf<C>::type *)A->masks, val, x, y,
+                           (T *)A->partial);
+    else
+        hipLaunchKernelGGL((k_spmv_stream<T, R, C, NVG, SPARSE>), dim3((unsigned)nwg), dim3(kWG),
+                           0, s, A->nrows, A->ncols, nt, tpw, nwg, remap, A->tile_p, A->tile_b,
+                           A->tile_v, A->tile_f, A->blk_ptr, A->blk_col,
+                           (const typename MaskOf<C>::type *)A->masks, val, x, y,
+                           (T *)A->partial);
     if (A->nsplit > 0) {
         const int64_t n = A->nsplit * R;
         hipLaunchKernelGGL(k_split_fixup<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
@@ -626,8 +819,10 @@ static hipError_t launch_stream_s(const spc5_matrix *A, const T *val, const T *x
 template <typename T, int R, int C>
 static hipError_t launch_stream(const spc5_matrix *A, const T *val, const T *x, T *y,
                                 hipStream_t s, int remap) {
-    return sparse_rows(A) ? launch_stream_s<T, R, C, true>(A, val, x, y, s, remap)
-                          : launch_stream_s<T, R, C, false>(A, val, x, y, s, remap);
+    if constexpr (R == 1) return launch_stream_s<T, R, C, false>(A, val, x, y, s, remap);
+    else
+        return sparse_rows(A) ? launch_stream_s<T, R, C, true>(A, val, x, y, s, remap)
+                              : launch_stream_s<T, R, C, false>(A, val, x, y, s, remap);
 }
 
 template <typename T>
