@@ -409,6 +409,83 @@ def batch_extras(dev, nmat=256, ks=(1, 4, 16)):
     return res
 
 
+def ablation_extras(dev, A_lap):
+    """The paper's ablations on this GPU.
+
+    (a) x load and row reduction (Sections 3.1, 3.2; the paper's comparison
+        table): the staged kernel with its single x load per block and the
+        cross-lane multi-reduction, against the partial x load (each row its
+        own x entries) and the per-row reduction, on the Laplacian 2048^2 and
+        a 48^3 x 3 FEM matrix, FP64;
+    (b) cost model (Section 4.3: a constant cost per block): forward times of
+        five matrices x six shapes fitted by least squares to
+        t = a*nblocks + b*nnz + c, with the GB/s and the nonzeros per block of
+        every point."""
+    import numpy as np
+    import torch
+
+    from paper_2307_14774_amd import spc5
+    from paper_2307_14774_amd import workloads as W
+    res = {}
+    log("ablation: generating matrices")
+    mats = {"laplacian2d_2048": A_lap, "fem3d_48x3": W.fem_3d(48, seed=1),
+            "zipf_graph_2^18": W.zipf_graph(1 << 18, seed=2),
+            "dense_2048": W.dense(2048, seed=3), "random10k": W.random_uniform(10_000, 10, seed=0)}
+
+    def one(M, x, y, n=20):
+        _, ms = time_launches(lambda: M.spmv(x, y), n, 3)
+        return _avg_us(ms)
+
+    table = {}
+    for name in ("laplacian2d_2048", "fem3d_48x3"):
+        A = mats[name]
+        x = torch.from_numpy(A.x).to(dev)
+        y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+        for rc in [(2, 4), (4, 4), (4, 8), (8, 8)]:
+            log(f"ablation: variants {name} beta{rc}")
+            M = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, *rc)
+            row = {}
+            for tag, v in (("single_x+multi_reduce", (False, False)),
+                           ("partial_x", (True, False)), ("per_row_reduce", (False, True)),
+                           ("partial_x+per_row_reduce", (True, True))):
+                M.set_variant(*v)
+                us = one(M, x, y)
+                row[tag] = {"launch_us": round(us, 2),
+                            "gbs": round(M.info.spmv_bytes / us / 1e3, 1)}
+            base = row["single_x+multi_reduce"]["launch_us"]
+            for tag in row:
+                row[tag]["speedup_of_default"] = round(row[tag]["launch_us"] / base, 3)
+            table[f"{name} beta({rc[0]},{rc[1]})"] = row
+            M.free()
+    res["x_load_and_reduction"] = table
+
+    pts = []
+    for name, A in mats.items():
+        x = torch.from_numpy(A.x).to(dev)
+        y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+        for rc in [(1, 8), (1, 16), (2, 4), (4, 4), (4, 8), (8, 8)]:
+            log(f"ablation: model {name} beta{rc}")
+            M = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, *rc)
+            us = one(M, x, y)
+            inf = M.info
+            pts.append({"matrix": name, "beta": list(rc), "nblocks": inf.nblocks, "nnz": inf.nnz,
+                        "nnz_per_block": round(inf.nnz / max(inf.nblocks, 1), 3),
+                        "fill": round(inf.fill, 4), "launch_us": round(us, 2),
+                        "gbs": round(inf.spmv_bytes / us / 1e3, 1),
+                        "gflops": round(2.0 * inf.nnz / us / 1e3, 1)})
+            M.free()
+    X = np.array([[p["nblocks"], p["nnz"], 1.0] for p in pts], dtype=np.float64)
+    t = np.array([p["launch_us"] for p in pts], dtype=np.float64)
+    coef, *_ = np.linalg.lstsq(X, t, rcond=None)
+    pred = X @ coef
+    r2 = 1.0 - float(((t - pred) ** 2).sum() / ((t - t.mean()) ** 2).sum())
+    res["cost_model"] = {"fit": "t_us = a*nblocks + b*nnz + c",
+                         "a_ps_per_block": round(coef[0] * 1e6, 3),
+                         "b_ps_per_nnz": round(coef[1] * 1e6, 3),
+                         "c_us": round(coef[2], 2), "r2": round(r2, 4), "points": pts}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -419,7 +496,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--skip", default="", help="comma list of extras to skip: "
-                    "kernels,formats,csr,flushed,fem,backward,batch")
+                    "kernels,formats,csr,flushed,fem,backward,batch,ablation")
     ap.add_argument("--batch-mats", type=int, default=256)
     ap.add_argument("--calibration-copy", action="store_true",
                     help="before timing, negate a 1 GiB float64 buffer 3 times (a plain "
@@ -502,7 +579,7 @@ def main():
         "parity_rel_l2": prim["rel_l2"],
     }
     extras = set() if args.no_extras else {"kernels", "formats", "csr", "flushed", "fem",
-                                           "backward", "batch"} - skip
+                                           "backward", "batch", "ablation"} - skip
     if "kernels" in extras:
         prim["kernel"] = M.kernel
         kern = {M.kernel: prim}
@@ -566,6 +643,8 @@ def main():
         out["backward"] = backward_extras(dev)
     if "batch" in extras:
         out["batch"] = batch_extras(dev, args.batch_mats)
+    if "ablation" in extras:
+        out["ablation"] = ablation_extras(dev, A)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(A, rc, args.cpu_budget)

@@ -84,7 +84,7 @@ typedef struct {
     /* transposed-product plan (spc5_prepare_transpose); all 0 without one */
     int transpose_r, transpose_c; /* beta(r,c) of the stored A^T */
     int transpose_kernel;     /* forward kernel run over A^T (spc5_kernel) */
-    int transpose_pad;        /* reserved, 0 */
+    int variant;              /* staged-kernel variant flags (spc5_set_variant) */
     int64_t transpose_bytes;  /* algorithmic bytes of one x_bar = A^T y_bar
                                  through the plan (without the value gather) */
     int64_t split_panels;     /* panels longer than one staged tile, cut into
@@ -150,6 +150,22 @@ typedef enum {
  * length).  Not safe to call while compute calls
  * on A are in flight. */
 int spc5_set_schedule(spc5_matrix *A, int kernel, int panels_per_tile);
+
+/* Kernel variants of the staged forward product that reproduce the paper's
+ * ablations (Table "res:perf:comp"); 0 restores the default.  Flags:
+ *  SPC5_VARIANT_PARTIAL_X   "partial x load" (Section 3.1): every row loads
+ *      its own x entries from memory, instead of the default single x load
+ *      per block shared by the block's r rows;
+ *  SPC5_VARIANT_ROW_REDUCE  per-row reduction (Section 3.2): the partial
+ *      sums of a row are added one after the other through LDS, instead of
+ *      the default multi-reduction (one cross-lane butterfly reducing every
+ *      row of the tile together).
+ * Results stay within the accuracy of the default (summation order only).
+ * Errors: SPC5_EINVAL (NULL A, unknown flags), SPC5_EUNSUPPORTED (the matrix
+ * does not use the staged kernel, or r not in {2,4,8}, or c > 8). */
+#define SPC5_VARIANT_PARTIAL_X 1
+#define SPC5_VARIANT_ROW_REDUCE 2
+int spc5_set_variant(spc5_matrix *A, int flags);
 
 /* ---------------------------------------------------------------- compute */
 

@@ -250,6 +250,7 @@ int spc5_get_info(const spc5_matrix *A, spc5_info *out) {
     out->device_bytes = vb * A->nnz + 4 * A->nblocks + (int64_t)A->r * A->mask_bytes * A->nblocks +
                         8 * (A->npanels + 1);
     out->split_panels = A->kernel == SPC5_KERNEL_STAGED ? A->nsplit : 0;
+    out->variant = A->variant;
     if (const spc5_matrix *T = A->tr) {
         out->transpose_r = T->r;
         out->transpose_c = T->c;
@@ -299,6 +300,7 @@ int spc5_set_schedule(spc5_matrix *A, int kernel, int ppt) {
     if ((kernel == SPC5_KERNEL_STAGED || kernel == SPC5_KERNEL_ROWS) && !x_fits_buffer(A))
         return fail(SPC5_EUNSUPPORTED, "x exceeds 2 GiB: only the sweep kernel applies");
     A->kernel = kernel == SPC5_KERNEL_AUTO ? auto_kernel(A) : kernel;
+    if (A->kernel != SPC5_KERNEL_STAGED) A->variant = 0;
     if (A->kernel == SPC5_KERNEL_STAGED) {
         DeviceGuard g(A->device);
         return build_staged_schedule(A, ppt);
@@ -348,6 +350,20 @@ int spc5_spmv_transpose_values(const spc5_matrix *A, const void *values, const v
                          : launch_transpose(A, values ? values : A->val, ybar, xbar,
                                             (hipStream_t)stream);
     return e == hipSuccess ? SPC5_OK : hip_fail(e, "spc5_spmv_transpose launch");
+}
+
+int spc5_set_variant(spc5_matrix *A, int flags) {
+    if (!A) return fail(SPC5_EINVAL, "A is NULL");
+    if (flags < 0 || flags > (SPC5_VARIANT_PARTIAL_X | SPC5_VARIANT_ROW_REDUCE))
+        return fail(SPC5_EINVAL, "unknown variant flags %d", flags);
+    if (flags != 0) {
+        if (A->kernel != SPC5_KERNEL_STAGED)
+            return fail(SPC5_EUNSUPPORTED, "variants apply to the staged kernel only");
+        if (!(A->r == 2 || A->r == 4 || A->r == 8) || A->c > 8)
+            return fail(SPC5_EUNSUPPORTED, "variants exist for r in {2,4,8}, c <= 8");
+    }
+    A->variant = flags;
+    return SPC5_OK;
 }
 
 int spc5_prepare_transpose(spc5_matrix *A, int r, int c) {

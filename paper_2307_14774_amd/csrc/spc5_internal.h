@@ -28,6 +28,7 @@ struct spc5_matrix {
     int64_t ntiles_staged = 0;
     int max_tile_values = 0;       // largest tile, in values
     bool staged_ok = false;        // the staged schedule exists
+    int variant = 0;               // staged-kernel ablation variant (spc5_set_variant)
     // panels longer than a tile: panel, first and last piece tile
     int32_t *split_p = nullptr, *split_t0 = nullptr, *split_t1 = nullptr;   // [nsplit]
     int64_t nsplit = 0;

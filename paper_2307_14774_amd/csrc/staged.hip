@@ -72,6 +72,10 @@ void staged_caps(const spc5_matrix *A, int *vt, int *bt, int *ppw) {
     *ppw = kWG / A->r;
 }
 
+// Kernel variants for the paper's ablations (spc5_set_variant).
+constexpr int kVarPartialX = 1;    // each row loads its own x (Section 3.1)
+constexpr int kVarRowReduce = 2;   // per-row sums of the sub-lanes (Section 3.2)
+
 // Row masks of block t in LDS (bytes of block t start at t*R*MB): the mask of
 // row i, the popcount of the rows below i and of the whole block.
 template <int R, int C>
@@ -193,10 +197,12 @@ struct TileStage {
 // sub-lanes per row (np*R*S <= 256 and S*R <= 64, so the butterfly stays in
 // a wavefront).  Returns the row sum on every sub-lane; `lead` marks the
 // sub-lane that stores it.
-template <typename T, int R, int C, int U, bool SPARSE>
+template <typename T, int R, int C, int U, bool SPARSE, int VAR = 0>
 __device__ __forceinline__ T tile_rows(int np, int b0, int b1, const int *sbp, const uint8_t *smb,
                                        const int *s_boff, const T *sval, const T *s_x,
-                                       const T *s_zero, int &pl_out, int &i_out, bool &lead) {
+                                       const T *s_zero, int &pl_out, int &i_out, bool &lead,
+                                       const int *scol = nullptr, const Buf *xbuf = nullptr,
+                                       T *s_red = nullptr) {
     const int th = threadIdx.x;
     int lgS = 0;
     if ((R & (R - 1)) == 0)
@@ -250,13 +256,22 @@ __device__ __forceinline__ T tile_rows(int np, int b0, int b1, const int *sbp, c
             // row's first value plus the popcount of the lower bits
 #pragma unroll
             for (int u = 0; u < U; ++u) {
+                const int c0u = (VAR & kVarPartialX) ? scol[tt[u]] : 0;
 #pragma unroll
                 for (int k = 0; k < C; ++k) {
                     const bool on = (m[u] >> k) & 1u;
                     const int jk = k ? j[u] + __popc(m[u] & ((1u << k) - 1u)) : j[u];
                     const T *pv = on ? sval + jk : s_zero;
-                    const T *px = on ? s_x + tt[u] * C + k : s_zero;
-                    acc[u] = fma(*pv, *px, acc[u]);
+                    if constexpr (VAR & kVarPartialX) {
+                        // partial x load: this row's own x entries, straight
+                        // from memory (a clear bit moves no data)
+                        const T xv = buf_load<T>(
+                            *xbuf, on ? (uint32_t)(c0u + k) * (uint32_t)sizeof(T) : kOOB);
+                        acc[u] = fma(*pv, xv, acc[u]);
+                    } else {
+                        const T *px = on ? s_x + tt[u] * C + k : s_zero;
+                        acc[u] = fma(*pv, *px, acc[u]);
+                    }
                 }
             }
         }
@@ -264,15 +279,28 @@ __device__ __forceinline__ T tile_rows(int np, int b0, int b1, const int *sbp, c
     T accs = acc[0];
 #pragma unroll
     for (int u = 1; u < U; ++u) accs += acc[u];
-    // sub-lanes of a row are R apart inside one wavefront
-    for (int d = R; d < lps; d <<= 1) accs += __shfl_xor(accs, d);
+    if constexpr (VAR & kVarRowReduce) {
+        // per-row reduction: the sub-lane partials go through LDS and the
+        // row's lead thread adds them one after the other
+        s_red[th] = accs;
+        __syncthreads();
+        if (live && sub == 0) {
+            T r = T(0);
+            for (int q = 0; q < S; ++q) r += s_red[pl * lps + q * R + i];
+            accs = r;
+        }
+    } else {
+        // multi-reduction: one butterfly step reduces every row of the tile
+        // at once (sub-lanes of a row are R apart inside one wavefront)
+        for (int d = R; d < lps; d <<= 1) accs += __shfl_xor(accs, d);
+    }
     pl_out = pl;
     i_out = i;
     lead = live && sub == 0;
     return accs;
 }
 
-template <typename T, int R, int C, int NVG, bool SPARSE>
+template <typename T, int R, int C, int NVG, bool SPARSE, int VAR>
 __global__ __launch_bounds__(kWG) void k_spmv_stream(
     int64_t nrows, int64_t ncols, int64_t ntiles, int tiles_per_wg, int64_t nwg, int remap,
     const int32_t *__restrict__ tile_p, const int32_t *__restrict__ tile_b,
@@ -292,6 +320,7 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
     __shared__ int s_boff[BT];
     __shared__ int s_wsum[kWG / kWave];
     __shared__ T s_zero[1];
+    __shared__ T s_red[(VAR & kVarRowReduce) ? kWG : 1];
 
     const int th = threadIdx.x;
     const int lane = lane_id();
@@ -341,9 +370,14 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
         const int col0 = has ? scol[tb] : 0;
         T xw[C];
 #pragma unroll
-        for (int k = 0; k < C; ++k)
-            xw[k] = buf_load<T>(xbuf, ((un >> k) & 1u) ? (uint32_t)(col0 + k) * (uint32_t)sizeof(T)
-                                                       : kOOB);
+        for (int k = 0; k < C; ++k) {
+            if constexpr (VAR & kVarPartialX)
+                xw[k] = T(0);   // no shared x windows: rows load their own
+            else
+                xw[k] = buf_load<T>(xbuf, ((un >> k) & 1u)
+                                              ? (uint32_t)(col0 + k) * (uint32_t)sizeof(T)
+                                              : kOOB);
+        }
         // ... then the next tile's staging loads, so both are in flight
         // together and waiting for the gathers does not wait for them (the
         // scheduling barriers keep the compiler from reordering the groups).
@@ -379,8 +413,9 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
         // 4. rows and 5. butterfly, then one store per row
         int pl, i;
         bool lead;
-        const T accs = tile_rows<T, R, C, U, SPARSE>(np, b0, b1, sbp, smb, s_boff, sval, s_x,
-                                                     s_zero, pl, i, lead);
+        const T accs = tile_rows<T, R, C, U, SPARSE, VAR>(np, b0, b1, sbp, smb, s_boff, sval,
+                                                          s_x, s_zero, pl, i, lead, scol, &xbuf,
+                                                          s_red);
         if (lead) {
             const int64_t row = (int64_t)(p0 + pl) * R + i;
             if (f0) partial[t * R + i] = accs;    // summed by k_split_fixup
@@ -757,7 +792,7 @@ int build_staged_schedule(spc5_matrix *A, int ppw_req) {
 
 // ---------------------------------------------------------------- launch
 
-template <typename T, int R, int C, int NVG, bool SPARSE>
+template <typename T, int R, int C, int NVG, bool SPARSE, int VAR = 0>
 static hipError_t launch_stream_g(const spc5_matrix *A, const T *val, const T *x, T *y,
                                   hipStream_t s, int remap) {
     const int64_t nt = A->ntiles_staged;
@@ -780,7 +815,7 @@ static hipError_t launch_stream_g(const spc5_matrix *A, const T *val, const T *x
                            (const typename MaskOf<C>::type *)A->masks, val, x, y,
                            (T *)A->partial);
     else
-        hipLaunchKernelGGL((k_spmv_stream<T, R, C, NVG, SPARSE>), dim3((unsigned)nwg), dim3(kWG),
+        hipLaunchKernelGGL((k_spmv_stream<T, R, C, NVG, SPARSE, VAR>), dim3((unsigned)nwg), dim3(kWG),
                            0, s, A->nrows, A->ncols, nt, tpw, nwg, remap, A->tile_p, A->tile_b,
                            A->tile_v, A->tile_f, A->blk_ptr, A->blk_col,
                            (const typename MaskOf<C>::type *)A->masks, val, x, y,
@@ -819,6 +854,23 @@ static hipError_t launch_stream_s(const spc5_matrix *A, const T *val, const T *x
 template <typename T, int R, int C>
 static hipError_t launch_stream(const spc5_matrix *A, const T *val, const T *x, T *y,
                                 hipStream_t s, int remap) {
+    // ablation variants: compiled for the paper's main shapes only
+    constexpr bool kVarShape = (R == 2 || R == 4 || R == 8) && (C == 4 || C == 8);
+    if (A->variant != 0) {
+        if constexpr (kVarShape) {
+            switch (A->variant) {
+                case kVarPartialX:
+                    return launch_stream_g<T, R, C, 4, false, kVarPartialX>(A, val, x, y, s, remap);
+                case kVarRowReduce:
+                    return launch_stream_g<T, R, C, 4, false, kVarRowReduce>(A, val, x, y, s,
+                                                                            remap);
+                default:
+                    return launch_stream_g<T, R, C, 4, false, kVarPartialX | kVarRowReduce>(
+                        A, val, x, y, s, remap);
+            }
+        }
+        return hipErrorInvalidValue;
+    }
     if constexpr (R == 1) return launch_stream_s<T, R, C, false>(A, val, x, y, s, remap);
     else
         return sparse_rows(A) ? launch_stream_s<T, R, C, true>(A, val, x, y, s, remap)

@@ -23,6 +23,7 @@ STATUS = {0: "SPC5_OK", -1: "SPC5_EINVAL", -2: "SPC5_EBADCSR", -3: "SPC5_ENOMEM"
 # every symbol include/spc5.h declares
 EXPORTS = [
     "csr_to_spc5", "spc5_free", "spc5_get_info", "spc5_export", "spc5_set_schedule",
+    "spc5_set_variant",
     "spc5_spmv", "spc5_spmv_values", "spc5_spmv_transpose", "spc5_spmv_transpose_values",
     "spc5_prepare_transpose", "spc5_values_grad", "spc5_spmm", "spc5_batch_create", "spc5_batch_free",
     "spc5_batch_set_operands", "spc5_batch_run", "spc5_batch_spmm", "spc5_plan",
@@ -47,7 +48,7 @@ class spc5_info(ctypes.Structure):
                 ("fill", ctypes.c_double), ("spmv_bytes", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("transpose_r", ctypes.c_int),
                 ("transpose_c", ctypes.c_int), ("transpose_kernel", ctypes.c_int),
-                ("transpose_pad", ctypes.c_int), ("transpose_bytes", ctypes.c_int64),
+                ("variant", ctypes.c_int), ("transpose_bytes", ctypes.c_int64),
                 ("split_panels", ctypes.c_int64)]
 
 
@@ -69,6 +70,7 @@ def lib():
         L.spc5_get_info.argtypes = [P, ctypes.POINTER(spc5_info)]
         L.spc5_export.argtypes = [P, P, P, P, P]
         L.spc5_set_schedule.argtypes = [P, I, I]
+        L.spc5_set_variant.argtypes = [P, I]
         L.spc5_spmv.argtypes = [P, P, P, P]
         L.spc5_spmv_values.argtypes = [P, P, P, P, P]
         L.spc5_spmv_transpose.argtypes = [P, P, P, P]
@@ -197,6 +199,12 @@ class Spc5Matrix:
         code = {"auto": KERNEL_AUTO, "rows": KERNEL_ROWS, "sweep": KERNEL_SWEEP,
                 "staged": KERNEL_STAGED}[kernel]
         _check(lib().spc5_set_schedule(self._h, code, panels_per_tile))
+        self.info = self._info()
+
+    def set_variant(self, partial_x: bool = False, row_reduce: bool = False):
+        """Ablation variants of the staged kernel (partial x load, per-row
+        reduction); both False restores the default."""
+        _check(lib().spc5_set_variant(self._h, (1 if partial_x else 0) | (2 if row_reduce else 0)))
         self.info = self._info()
 
     @property

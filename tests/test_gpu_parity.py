@@ -278,6 +278,51 @@ def test_split_transpose_plan_zipf(dev):
     assert oracle.rel_l2(xb, ref) <= 1e-14
 
 
+@pytest.mark.parametrize("A", [CASES[-6], CASES[-5], CASES[-2]], ids=lambda a: a.name)
+@pytest.mark.parametrize("rc", [(2, 4), (4, 4), (4, 8), (8, 8), (2, 3)], ids=lambda t: "b%d_%d" % t)
+@pytest.mark.parametrize("variant", [(True, False), (False, True), (True, True)],
+                         ids=["partial_x", "row_reduce", "both"])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_staged_variants(A, rc, variant, dtype, dev):
+    """The ablation variants (partial x load, per-row reduction) compute the
+    same product: against the oracle and reproducible."""
+    r, c = rc
+    S = spc5()
+    say(f"variant {variant} {A.name} beta{rc} {dtype}")
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c, dtype)
+    M.set_schedule("staged")
+    M.set_variant(*variant)
+    assert M.info.variant == (1 if variant[0] else 0) | (2 if variant[1] else 0)
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    x = to_dev(A.x, dev, tdt)
+    y = M.spmv(x).cpu().numpy()
+    assert np.array_equal(M.spmv(x).cpu().numpy(), y)
+    if dtype == "float64":
+        ref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
+        assert oracle.rel_l2(y, ref) <= 1e-14
+    else:
+        ref = oracle.csr_spmv(A.rowptr, A.colidx, A.values.astype(np.float32).astype(np.float64),
+                              A.x.astype(np.float32).astype(np.float64))
+        assert oracle.rel_l2(y, ref) <= 1e-6
+    M.set_variant()
+    assert M.info.variant == 0
+
+
+def test_variant_errors(dev):
+    S = spc5()
+    A = W.random_sparse(50, 40, 0.1, seed=28)
+    M1 = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 1, 8)
+    with pytest.raises(S.Spc5Error) as ei:
+        M1.set_variant(partial_x=True)
+    assert ei.value.status == -5
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 4, 4)
+    M.set_schedule("sweep")
+    with pytest.raises(S.Spc5Error) as ei:
+        M.set_variant(row_reduce=True)
+    assert ei.value.status == -5
+    assert S.lib().spc5_set_variant(M.handle, 7) == -1
+
+
 # ------------------------------------------------------------ backward
 
 @pytest.mark.parametrize("A", CASES[4:], ids=lambda a: a.name)
