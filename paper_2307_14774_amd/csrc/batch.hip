@@ -9,6 +9,7 @@
 // be recorded in a HIP graph and replayed.
 #include "spc5_internal.h"
 #include "spmm_tile.h"
+#include "stage.h"
 
 #include <algorithm>
 #include <vector>
@@ -20,11 +21,19 @@ struct spc5_batch {
     std::vector<spc5_matrix *> mats;
     // bound operands
     int nrhs = 0, kchunk = 0;
+    bool vmode = false;            // every matrix beta(1,c): value-mode tiles
+    int nch = 0;                   // right-hand-side chunks per tile (value mode)
     int64_t nwork = 0;
-    void *d_desc = nullptr;        // BatchDesc[nmat]
+    void *d_desc = nullptr;        // BatchDesc[nmat] or BatchDescV[nmat]
     int32_t *d_work = nullptr;     // matrix of each work item
+    void *d_fix = nullptr;         // BatchFix[nfix]: rows of split panels
+    int64_t nfix = 0;
+    void *d_partial = nullptr;     // [nwork * kchunk] partial row sums of pieces
     unsigned *d_counter = nullptr;
     int grid = 0;
+    // batch-private staged schedules with full-size tiles (value mode): the
+    // schedule fields of these shallow copies only
+    std::vector<spc5_matrix> sched;
 };
 
 namespace spc5 {
@@ -70,7 +79,7 @@ __global__ __launch_bounds__(kWave) void k_batch(const BatchDesc *__restrict__ d
     for (;;) {
         if (lane_id() == 0) s_w = atomicAdd(counter, 1u);
         __syncthreads();
-        const int64_t w = s_w;
+        const int64_t w = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)s_w);
         __syncthreads();
         if (w >= nwork) break;
         const BatchDesc d = descs[work[w]];
@@ -90,6 +99,291 @@ __global__ __launch_bounds__(kWave) void k_batch(const BatchDesc *__restrict__ d
     }
 }
 
+// ---------------------------------------------------------------- value mode
+
+// A matrix of a value-mode batch: its staged tile schedule and operands.
+struct BatchDescV {
+    const int32_t *tile_p, *tile_b, *tile_v, *tile_f;
+    const int32_t *blk_ptr, *blk_col;
+    const void *masks, *val;
+    const void *X;
+    void *Y;
+    int64_t nrows, ncols, w0;   // w0: first work item of the matrix
+    int cclass;                 // c rounded up to 4, 8 or 16
+    int pad;
+};
+
+// A split panel (a row longer than one tile) of a value-mode batch: the
+// partial sums of its piece tiles t0..t1 are added in tile order.
+struct BatchFix {
+    int32_t mat, row, t0, t1;
+};
+
+// Shared memory of one value-mode tile (sized for the widest mask type).
+template <typename T>
+struct VTileLds {
+    using Cfg = StreamCfg<T, 1, 16, 4>;
+    static constexpr int VCAP = Cfg::VVEC * 16 / (int)sizeof(T);
+    v4u val[Cfg::VVEC];
+    v4u mask[Cfg::MVEC];
+    v4u col[Cfg::CVEC];
+    v4u bp[Cfg::PVEC];
+    int vcol[VCAP];
+    int boff[Cfg::BT + 1];
+    int wsum[kWG / kWave];
+    int longrow[kWG];
+    int nlong;
+};
+
+// Staging registers of one value-mode tile whose masks are mb bytes wide
+// (1 for c <= 8, 2 above); register counts are those of the widest case.
+template <typename T>
+struct BStage {
+    using Cfg = StreamCfg<T, 1, 16, 4>;
+    Range16 qv, qm, qc, qp;
+    RegStage<Cfg::NV> rv;
+    RegStage<Cfg::NM> rm;
+    RegStage<Cfg::NC> rc;
+    RegStage<Cfg::NP> rp;
+    template <int N>
+    __device__ __forceinline__ static void fixed(RegStage<N> &st, const Range16 &q) {
+        const uint32_t th16 = (uint32_t)threadIdx.x * 16u;
+#pragma unroll
+        for (int g = 0; g < N; ++g) st.r[g] = buf_load16(q.buf, th16 + (uint32_t)(kWG * 16 * g));
+    }
+    __device__ __forceinline__ void issue(const BatchDescV &d, const TileBounds &b, int mb) {
+        qv = range16(d.val, (int64_t)b.v0 * (int64_t)sizeof(T), (int64_t)b.v1 * (int64_t)sizeof(T));
+        qm = range16(d.masks, (int64_t)b.b0 * mb, (int64_t)b.b1 * mb);
+        qc = range16(d.blk_col, (int64_t)b.b0 * 4, (int64_t)b.b1 * 4);
+        qp = range16(d.blk_ptr, (int64_t)b.p0 * 4, (int64_t)(b.p1 + 1) * 4);
+        fixed(rv, qv);
+        fixed(rm, qm);
+        fixed(rc, qc);
+        fixed(rp, qp);
+    }
+    __device__ __forceinline__ void commit(VTileLds<T> &L) const {
+        rm.commit(L.mask, qm);
+        rc.commit(L.col, qc);
+        rp.commit(L.bp, qp);
+        rv.commit(L.val, qv);
+    }
+};
+
+// KC consecutive entries of row `row` of X (leading dimension ld).
+template <typename T, int KC>
+__device__ __forceinline__ void load_xrow(const Buf &xb, int64_t row, int ld, int t0, T *out) {
+    const uint32_t off = (uint32_t)((row * ld + t0) * (int64_t)sizeof(T));
+    if constexpr (KC == 1) {
+        out[0] = buf_load<T>(xb, off);
+    } else {
+        constexpr int NV = KC * (int)sizeof(T) / 16;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const v4u v = buf_load16(xb, off + 16u * q);
+            if constexpr (sizeof(T) == 8) {
+                typedef double v2d __attribute__((ext_vector_type(2)));
+                const v2d f = __builtin_bit_cast(v2d, v);
+                out[2 * q] = f.x;
+                out[2 * q + 1] = f.y;
+            } else {
+                typedef float v4f __attribute__((ext_vector_type(4)));
+                const v4f f = __builtin_bit_cast(v4f, v);
+                out[4 * q] = f.x;
+                out[4 * q + 1] = f.y;
+                out[4 * q + 2] = f.z;
+                out[4 * q + 3] = f.w;
+            }
+        }
+    }
+}
+
+// The bounds are uniform; readfirstlane keeps them (and the staging ranges
+// computed from them) in scalar registers.
+__device__ __forceinline__ TileBounds item_bounds(const BatchDescV &d, int64_t tile) {
+    TileBounds b = tile_bounds(tile, d.tile_p, d.tile_b, d.tile_v, d.tile_f);
+    b.f = __builtin_amdgcn_readfirstlane(b.f);
+    b.p0 = __builtin_amdgcn_readfirstlane(b.p0);
+    b.p1 = __builtin_amdgcn_readfirstlane(b.p1);
+    b.b0 = __builtin_amdgcn_readfirstlane(b.b0);
+    b.b1 = __builtin_amdgcn_readfirstlane(b.b1);
+    b.v0 = __builtin_amdgcn_readfirstlane(b.v0);
+    b.v1 = __builtin_amdgcn_readfirstlane(b.v1);
+    return b;
+}
+
+// Persistent value-mode batch.  Workgroups take chunks of kGrab consecutive
+// (matrix, tile, chunk of KC right-hand sides) items from a device counter
+// until the list is exhausted; inside a chunk the next item is staged while
+// the current one is computed, as in the single-matrix value-mode kernel.
+// Per item: block popcount scan, column decode, then for one right-hand side
+// one x load per value slot (all in flight together) and in-place products
+// summed per row; for KC right-hand sides each row walks its values with
+// KC-wide x loads.  A butterfly over the S sub-lanes of a row, one store.
+constexpr int kGrab = 4;
+
+template <typename T, int KC>
+__global__ __launch_bounds__(kWG) void k_batch_v(const BatchDescV *__restrict__ descs,
+                                                 const int32_t *__restrict__ work, int64_t nwork,
+                                                 unsigned *counter, int nch, int ld,
+                                                 T *__restrict__ partial) {
+    __shared__ VTileLds<T> L;
+    __shared__ unsigned s_w;
+    constexpr int VCAP = VTileLds<T>::VCAP;
+    constexpr int NX = (VCAP + kWG - 1) / kWG;
+    constexpr int BPT = StreamCfg<T, 1, 16, 4>::BPT;
+    const int th = threadIdx.x;
+    const int lane = lane_id();
+    const int wv = th / kWave;
+    for (;;) {
+        if (th == 0) s_w = atomicAdd(counter, (unsigned)kGrab);
+        __syncthreads();
+        // uniform by construction; readfirstlane lets the compiler keep the
+        // item's descriptor and pointers in scalar registers
+        const int64_t wbase = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)s_w);
+        __syncthreads();
+        if (wbase >= nwork) break;
+        const int64_t wend = min(wbase + kGrab, nwork);
+
+        BatchDescV d = descs[work[wbase]];
+        int64_t local = wbase - d.w0;
+        TileBounds b = item_bounds(d, local / nch);
+        int mb = d.cclass > 8 ? 2 : 1;
+        BStage<T> st;
+        st.issue(d, b, mb);
+
+        for (int64_t w = wbase; w < wend; ++w) {
+            const int t0 = (int)(local % nch) * KC;
+            // the next item (the current one again past the chunk's end)
+            const int64_t wn = w + 1 < wend ? w + 1 : w;
+            const BatchDescV dn = descs[work[wn]];
+            const int64_t localn = wn - dn.w0;
+            const TileBounds bn = item_bounds(dn, localn / nch);
+            const int mbn = dn.cclass > 8 ? 2 : 1;
+
+            __syncthreads();
+            st.commit(L);
+            if (th == 0) L.nlong = 0;
+            __syncthreads();
+            const uint8_t *smk = (const uint8_t *)L.mask + st.qm.skew;
+            const int *scol = (const int *)((const uint8_t *)L.col + st.qc.skew);
+            const int *sbp = (const int *)((const uint8_t *)L.bp + st.qp.skew);
+            T *sval = (T *)((uint8_t *)L.val + st.qv.skew);
+            const int np = b.p1 - b.p0, nbt = b.b1 - b.b0, nv = b.v1 - b.v0;
+
+            // block value offsets and value columns
+            unsigned m[BPT];
+            int cnt[BPT], own = 0;
+#pragma unroll
+            for (int q = 0; q < BPT; ++q) {
+                const int tb = BPT * th + q;
+                m[q] = tb < nbt ? (mb == 1 ? (unsigned)smk[tb]
+                                           : (unsigned)((const uint16_t *)smk)[tb])
+                                : 0u;
+                cnt[q] = __popc(m[q]);
+                own += cnt[q];
+            }
+            const int incl = wave_incl_scan(own);
+            if (lane == kWave - 1) L.wsum[wv] = incl;
+            __syncthreads();
+            int before = 0, total = 0;
+#pragma unroll
+            for (int w2 = 0; w2 < kWG / kWave; ++w2) {
+                before += w2 < wv ? L.wsum[w2] : 0;
+                total += L.wsum[w2];
+            }
+            int boff = before + incl - own;
+            if (th == 0) L.boff[nbt] = total;
+#pragma unroll
+            for (int q = 0; q < BPT; ++q) {
+                const int tb = BPT * th + q;
+                if (tb < nbt) {
+                    L.boff[tb] = boff;
+                    const int c0b = scol[tb];
+                    unsigned mm = m[q];
+                    int v = boff;
+                    while (mm) {
+                        L.vcol[v++] = c0b + __ffs(mm) - 1;
+                        mm &= mm - 1u;
+                    }
+                }
+                boff += cnt[q];
+            }
+            __syncthreads();
+
+            const Buf xb = make_buf(d.X, d.ncols * (int64_t)ld * (int64_t)sizeof(T));
+            auto range = [&](int pl, int &vs, int &ve) {
+                vs = L.boff[max(sbp[pl], b.b0) - b.b0];
+                ve = L.boff[min(sbp[pl + 1], b.b1) - b.b0];
+            };
+            auto emit = [&](int pl, const T *acc) {
+                const int64_t row = (int64_t)(b.p0 + pl);
+#pragma unroll
+                for (int q = 0; q < KC; ++q) {
+                    if (b.f) partial[w * KC + q] = acc[q];    // summed by k_batch_fix
+                    else if (row < d.nrows) ((T *)d.Y)[row * ld + t0 + q] = acc[q];
+                }
+            };
+            if constexpr (KC == 1) {
+                // one x load per value slot, then the next item's staging
+                T xg[NX];
+#pragma unroll
+                for (int k = 0; k < NX; ++k) {
+                    const int v = th + kWG * k;
+                    xg[k] = buf_load<T>(xb, v < nv ? (uint32_t)((int64_t)L.vcol[v] * ld + t0) *
+                                                         (uint32_t)sizeof(T)
+                                                   : kOOB);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                st.issue(dn, bn, mbn);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < NX; ++k) {
+                    const int v = th + kWG * k;
+                    if (v < nv) sval[v] = sval[v] * xg[k];
+                }
+                __syncthreads();
+                value_rows<T, 1>(np, range, [&](int v, T *acc) { acc[0] += sval[v]; }, emit,
+                                 L.longrow, &L.nlong);
+            } else {
+                __builtin_amdgcn_sched_barrier(0);
+                st.issue(dn, bn, mbn);
+                __builtin_amdgcn_sched_barrier(0);
+                value_rows<T, KC>(
+                    np, range,
+                    [&](int v, T *acc) {
+                        T xa[KC];
+                        load_xrow<T, KC>(xb, L.vcol[v], ld, t0, xa);
+                        const T a = sval[v];
+#pragma unroll
+                        for (int q = 0; q < KC; ++q) acc[q] = fma(a, xa[q], acc[q]);
+                    },
+                    emit, L.longrow, &L.nlong);
+            }
+            d = dn;
+            local = localn;
+            b = bn;
+            mb = mbn;
+        }
+    }
+}
+
+// Rows of split panels: partial sums of the pieces in tile order.
+template <typename T, int KC>
+__global__ void k_batch_fix(const BatchFix *__restrict__ fix, int64_t nfix,
+                            const BatchDescV *__restrict__ descs, int nch, int ld,
+                            const T *__restrict__ partial) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)nch * KC;
+    if (g >= nfix * per) return;
+    const BatchFix fx = fix[g / per];
+    const int rhs = (int)(g % per);
+    const int ch = rhs / KC, q = rhs % KC;
+    const BatchDescV &d = descs[fx.mat];
+    T acc = T(0);
+    for (int64_t t = fx.t0; t <= fx.t1; ++t) acc += partial[(d.w0 + t * nch + ch) * KC + q];
+    ((T *)d.Y)[(int64_t)fx.row * ld + rhs] = acc;
+}
+
 template <typename T, int K>
 static int batch_grid() {
     int dev = 0, blocks = 0;
@@ -101,8 +395,45 @@ static int batch_grid() {
     return blocks * prop.multiProcessorCount;
 }
 
+template <typename T, int KC>
+static int batch_grid_v() {
+    int dev = 0, blocks = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_v<T, KC>, kWG, 0) !=
+            hipSuccess || blocks < 1)
+        return 256 * 4;
+    return blocks * prop.multiProcessorCount;
+}
+
+template <typename T>
+static hipError_t launch_batch_v(const spc5_batch *B, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, B->d_counter);
+    const BatchDescV *d = (const BatchDescV *)B->d_desc;
+    if (B->kchunk == 4)
+        hipLaunchKernelGGL((k_batch_v<T, 4>), dim3(B->grid), dim3(kWG), 0, s, d, B->d_work,
+                           B->nwork, B->d_counter, B->nch, B->nrhs, (T *)B->d_partial);
+    else
+        hipLaunchKernelGGL((k_batch_v<T, 1>), dim3(B->grid), dim3(kWG), 0, s, d, B->d_work,
+                           B->nwork, B->d_counter, B->nch, B->nrhs, (T *)B->d_partial);
+    if (B->nfix > 0) {
+        const int64_t n = B->nfix * B->nrhs;
+        const unsigned g = (unsigned)((n + 255) / 256);
+        if (B->kchunk == 4)
+            hipLaunchKernelGGL((k_batch_fix<T, 4>), dim3(g), dim3(256), 0, s,
+                               (const BatchFix *)B->d_fix, B->nfix, d, B->nch, B->nrhs,
+                               (const T *)B->d_partial);
+        else
+            hipLaunchKernelGGL((k_batch_fix<T, 1>), dim3(g), dim3(256), 0, s,
+                               (const BatchFix *)B->d_fix, B->nfix, d, B->nch, B->nrhs,
+                               (const T *)B->d_partial);
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t launch_batch(const spc5_batch *B, hipStream_t s) {
+    if (B->vmode) return launch_batch_v<T>(B, s);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, B->d_counter);
     const BatchDesc *d = (const BatchDesc *)B->d_desc;
     switch (B->kchunk) {
@@ -123,16 +454,95 @@ static hipError_t launch_batch(const spc5_batch *B, hipStream_t s) {
 }
 
 static void drop_operands(spc5_batch *B) {
-    if (B->d_desc) (void)hipFree(B->d_desc);
-    if (B->d_work) (void)hipFree(B->d_work);
+    for (void *p : {B->d_desc, (void *)B->d_work, B->d_fix, B->d_partial})
+        if (p) (void)hipFree(p);
     B->d_desc = nullptr;
     B->d_work = nullptr;
+    B->d_fix = nullptr;
+    B->d_partial = nullptr;
     B->nwork = 0;
+    B->nfix = 0;
     B->nrhs = 0;
+    B->vmode = false;
 }
 
 int count_blocks_device(const int64_t *d_rowptr, const int32_t *d_colidx, int64_t nrows, int r,
                         int c, int64_t *nblocks);
+
+// Value-mode binding: every matrix is beta(1,c) with a staged schedule.
+// Work items are (matrix, staged tile, chunk of KC right-hand sides); the
+// split panels of all matrices form the fixup list.
+template <typename T>
+static int bind_value_mode(spc5_batch *B, int nrhs, const void *const *X, void *const *Y) {
+    const int KC = nrhs % 4 == 0 ? 4 : 1;
+    const int nch = nrhs / KC;
+    std::vector<BatchDescV> desc(B->nmat);
+    std::vector<int32_t> work;
+    std::vector<BatchFix> fix;
+    int64_t w0 = 0;
+    hipError_t e;
+    for (int m = 0; m < B->nmat; ++m) {
+        const spc5_matrix *A = B->mats[m];
+        const spc5_matrix *Sd = &B->sched[m];      // full-size tile schedule
+        BatchDescV &d = desc[m];
+        d.tile_p = Sd->tile_p;
+        d.tile_b = Sd->tile_b;
+        d.tile_v = Sd->tile_v;
+        d.tile_f = Sd->tile_f;
+        d.blk_ptr = A->blk_ptr;
+        d.blk_col = A->blk_col;
+        d.masks = A->masks;
+        d.val = A->val;
+        d.X = X[m];
+        d.Y = Y[m];
+        d.nrows = A->nrows;
+        d.ncols = A->ncols;
+        d.w0 = w0;
+        d.cclass = A->c <= 4 ? 4 : (A->c <= 8 ? 8 : 16);
+        d.pad = 0;
+        const int64_t items = Sd->ntiles_staged * nch;
+        if (w0 + items >= ((int64_t)1 << 31)) return fail(SPC5_EUNSUPPORTED, "too many tiles");
+        work.insert(work.end(), (size_t)items, (int32_t)m);
+        if (Sd->nsplit > 0) {
+            std::vector<int32_t> sp((size_t)Sd->nsplit), s0((size_t)Sd->nsplit),
+                s1((size_t)Sd->nsplit);
+            if ((e = hipMemcpy(sp.data(), Sd->split_p, sp.size() * 4, hipMemcpyDeviceToHost)) !=
+                    hipSuccess ||
+                (e = hipMemcpy(s0.data(), Sd->split_t0, s0.size() * 4, hipMemcpyDeviceToHost)) !=
+                    hipSuccess ||
+                (e = hipMemcpy(s1.data(), Sd->split_t1, s1.size() * 4, hipMemcpyDeviceToHost)) !=
+                    hipSuccess)
+                return hip_fail(e, "reading split panels");
+            for (size_t q = 0; q < sp.size(); ++q) fix.push_back({m, sp[q], s0[q], s1[q]});
+        }
+        w0 += items;
+    }
+    drop_operands(B);
+    const size_t nw = work.size();
+    if ((e = hipMalloc(&B->d_desc, sizeof(BatchDescV) * desc.size())) != hipSuccess ||
+        (e = hipMalloc((void **)&B->d_work, std::max<size_t>(4, nw * 4))) != hipSuccess ||
+        (!fix.empty() &&
+         ((e = hipMalloc(&B->d_fix, sizeof(BatchFix) * fix.size())) != hipSuccess ||
+          (e = hipMalloc(&B->d_partial, nw * (size_t)KC * sizeof(T))) != hipSuccess)) ||
+        (e = hipMemcpy(B->d_desc, desc.data(), sizeof(BatchDescV) * desc.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (nw > 0 && (e = hipMemcpy(B->d_work, work.data(), nw * 4, hipMemcpyHostToDevice)) !=
+                       hipSuccess) ||
+        (!fix.empty() && (e = hipMemcpy(B->d_fix, fix.data(), sizeof(BatchFix) * fix.size(),
+                                        hipMemcpyHostToDevice)) != hipSuccess)) {
+        drop_operands(B);
+        return hip_fail(e, "binding batch operands");
+    }
+    B->vmode = true;
+    B->nrhs = nrhs;
+    B->kchunk = KC;
+    B->nch = nch;
+    B->nwork = (int64_t)nw;
+    B->nfix = (int64_t)fix.size();
+    B->grid = KC == 4 ? batch_grid_v<T, 4>() : batch_grid_v<T, 1>();
+    B->grid = (int)std::max<int64_t>(1, std::min<int64_t>(B->grid, B->nwork));
+    return SPC5_OK;
+}
 
 }  // namespace spc5
 
@@ -163,6 +573,28 @@ int spc5_batch_create(int nmat, spc5_matrix *const *mats, spc5_batch **out) {
         delete B;
         return hip_fail(e, "creating the batch");
     }
+    // beta(1,c) batches run value-mode tiles from their own full-size
+    // schedules (a matrix's own schedule is sized for a launch of its own)
+    bool r1 = true;
+    for (int m = 0; m < nmat; ++m) r1 = r1 && mats[m]->r == 1;
+    if (r1) {
+        B->sched.resize(nmat);
+        for (int m = 0; m < nmat; ++m) {
+            spc5_matrix &S = B->sched[m];
+            const spc5_matrix *A = mats[m];
+            S.nrows = A->nrows; S.ncols = A->ncols; S.nnz = A->nnz;
+            S.nblocks = A->nblocks; S.npanels = A->npanels;
+            S.r = A->r; S.c = A->c; S.dtype = A->dtype; S.mask_bytes = A->mask_bytes;
+            S.device = A->device;
+            S.blk_ptr = A->blk_ptr; S.masks = A->masks; S.panel_val = A->panel_val;
+            const int st = build_staged_schedule(&S, 0, false);
+            S.blk_ptr = nullptr; S.masks = nullptr; S.panel_val = nullptr;
+            if (st != SPC5_OK) {
+                spc5_batch_free(B);
+                return st;
+            }
+        }
+    }
     *out = B;
     return SPC5_OK;
 }
@@ -170,6 +602,7 @@ int spc5_batch_create(int nmat, spc5_matrix *const *mats, spc5_batch **out) {
 void spc5_batch_free(spc5_batch *B) {
     if (!B) return;
     drop_operands(B);
+    for (spc5_matrix &S : B->sched) free_staged_schedule(&S);
     if (B->d_counter) (void)hipFree(B->d_counter);
     delete B;
 }
@@ -177,6 +610,19 @@ void spc5_batch_free(spc5_batch *B) {
 int spc5_batch_set_operands(spc5_batch *B, int nrhs, const void *const *X, void *const *Y) {
     if (!B || !X || !Y) return fail(SPC5_EINVAL, "NULL argument");
     if (nrhs < 1 || nrhs > 64) return fail(SPC5_EINVAL, "nrhs must be in 1..64");
+    // value mode when every matrix is beta(1,c) with a staged schedule and
+    // every X is addressable by a 2 GiB buffer range
+    bool vm = true;
+    const int64_t vb = B->dtype == SPC5_F64 ? 8 : 4;
+    for (int m = 0; m < B->nmat; ++m) {
+        const spc5_matrix *A = B->mats[m];
+        if ((!X[m] && A->ncols > 0) || (!Y[m] && A->nrows > 0))
+            return fail(SPC5_EINVAL, "NULL operand for matrix %d", m);
+        if (A->r != 1 || B->sched.empty() || A->ncols * nrhs * vb > kMaxBufBytes) vm = false;
+    }
+    if (vm)
+        return B->dtype == SPC5_F64 ? bind_value_mode<double>(B, nrhs, X, Y)
+                                    : bind_value_mode<float>(B, nrhs, X, Y);
     const int K = nrhs % 16 == 0 ? 16 : (nrhs % 4 == 0 ? 4 : 1);
     std::vector<BatchDesc> desc(B->nmat);
     std::vector<int32_t> work;

@@ -78,7 +78,7 @@ hipError_t launch_spmv_staged(const spc5_matrix *A, const void *val, const void 
                               hipStream_t s, int remap);
 // (Re)build the staged kernel's tile schedule with at most ppw panels per tile
 // (0: as many as one workgroup has rows for).
-int build_staged_schedule(spc5_matrix *A, int ppw);
+int build_staged_schedule(spc5_matrix *A, int ppw, bool shrink = true);
 void free_staged_schedule(spc5_matrix *A);
 hipError_t excl_scan_i64(const int64_t *in, int64_t n, int64_t *out, hipStream_t s,
                          int64_t **scratch);

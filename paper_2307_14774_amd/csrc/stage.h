@@ -1,0 +1,224 @@
+// Tile staging shared by the staged forward kernels and the batched
+// kernel: tile capacities, LDS mask helpers, and the 16-byte register
+// staging of a tile's contiguous ranges (values, row masks, anchors, panel
+// bounds) through raw buffer descriptors.
+#pragma once
+
+#include "spc5_internal.h"
+#include "wave.h"
+
+namespace spc5 {
+
+constexpr int kWG = 256;   // threads per workgroup (4 wavefronts)
+
+template <typename T, int R, int C, int NVG = 4>
+struct StreamCfg {
+    using MT = typename MaskOf<C>::type;
+    static constexpr int MB = (int)sizeof(MT);
+    // LDS bytes for the values of one tile: NVG 16-byte vectors per thread
+    static constexpr int VBYTES = 4096 * NVG;
+    static constexpr int VT = (16384 - 16) / (int)sizeof(T);           // schedule cap
+    static constexpr int BT0 = 8192 / (C * (int)sizeof(T));
+    // blocks per tile: bounded by the x windows in LDS (C per block); beta(1,c)
+    // keeps no windows (value mode) and gives each thread BPT blocks
+    static constexpr int BPT = R == 1 ? 4 : 1;
+    static constexpr int BT = R == 1 ? kWG * BPT : (BT0 < 256 ? BT0 : 256);
+    static constexpr int PPW = kWG / R;                                // panels per tile
+    static constexpr int VVEC = VBYTES / 16;
+    static constexpr int MVEC = (BT * R * MB + 30) / 16;
+    static constexpr int CVEC = (BT * 4 + 30) / 16;
+    static constexpr int PVEC = ((PPW + 1) * 4 + 30) / 16;
+    static constexpr int NV = VVEC / kWG;                              // vectors per thread
+    static constexpr int NM = (MVEC + kWG - 1) / kWG;
+    static constexpr int NC = (CVEC + kWG - 1) / kWG;
+    static constexpr int NP = (PVEC + kWG - 1) / kWG;
+    static constexpr int U = R * C <= 16 ? 4 : 2;                      // blocks per step
+};
+
+// Tile capacities for a matrix (must match StreamCfg).
+void staged_caps(const spc5_matrix *A, int *vt, int *bt, int *ppw);
+
+// Kernel variants for the paper's ablations (spc5_set_variant).
+constexpr int kVarPartialX = 1;    // each row loads its own x (Section 3.1)
+constexpr int kVarRowReduce = 2;   // per-row sums of the sub-lanes (Section 3.2)
+
+// Row masks of block t in LDS (bytes of block t start at t*R*MB): the mask of
+// row i, the popcount of the rows below i and of the whole block.
+template <int R, int C>
+__device__ __forceinline__ void lds_block_masks(const uint8_t *sm, int t, int i, unsigned &m,
+                                                int &pre, int &tot) {
+    using MT = typename MaskOf<C>::type;
+    constexpr int MB = (int)sizeof(MT);
+    constexpr int WB = R * MB;
+    if constexpr (WB == 1 || WB == 2 || WB == 4 || WB == 8) {
+        uint64_t w;
+        if constexpr (WB == 1) w = sm[t];
+        else if constexpr (WB == 2) w = *(const uint16_t *)(sm + 2 * t);
+        else if constexpr (WB == 4) w = *(const uint32_t *)(sm + 4 * t);
+        else w = *(const uint64_t *)(sm + 8 * t);
+        const int sh = i * 8 * MB;
+        m = (unsigned)(w >> sh) & ((1u << (8 * MB)) - 1u);
+        pre = __popcll(sh ? (w & ((1ull << sh) - 1ull)) : 0ull);
+        tot = __popcll(w);
+    } else {
+        m = 0;
+        pre = 0;
+        tot = 0;
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            unsigned mr;
+            if constexpr (MB == 1) mr = sm[t * R + rr];
+            else mr = ((const uint16_t *)sm)[t * R + rr];
+            const int pc = __popc(mr);
+            pre += rr < i ? pc : 0;
+            m = rr == i ? mr : m;
+            tot += pc;
+        }
+    }
+}
+
+// Union of the r row masks of block t (the columns the block touches).
+template <int R, int C>
+__device__ __forceinline__ unsigned lds_block_union(const uint8_t *sm, int t) {
+    using MT = typename MaskOf<C>::type;
+    constexpr int MB = (int)sizeof(MT);
+    unsigned u = 0;
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+        if constexpr (MB == 1) u |= sm[t * R + rr];
+        else u |= ((const uint16_t *)sm)[t * R + rr];
+    }
+    return u;
+}
+
+// A contiguous byte range of global memory, as 16-byte vectors from an
+// aligned base, addressed through a raw buffer descriptor whose record count
+// is the range's length: vector indices past the range read zeros, so the
+// staging loads need no clamping.
+struct Range16 {
+    Buf buf;
+    int n;       // vectors
+    int skew;    // bytes from the aligned base to the first wanted byte
+};
+
+__device__ __forceinline__ Range16 range16(const void *base, int64_t byte0, int64_t byte1) {
+    const int64_t a0 = byte0 & ~(int64_t)15;
+    Range16 r;
+    r.n = byte1 > byte0 ? (int)((byte1 - a0 + 15) >> 4) : 0;
+    r.skew = (int)(byte0 - a0);
+    r.buf = make_buf((const char *)base + a0, (int64_t)r.n * 16);
+    return r;
+}
+
+// Register stage of up to NVMAX vectors per thread and the matching LDS
+// stores.
+template <int NVMAX>
+struct RegStage {
+    v4u r[NVMAX];
+
+    __device__ __forceinline__ void commit(v4u *dst, const Range16 &q) const {
+        const int th = threadIdx.x;
+#pragma unroll
+        for (int g = 0; g < NVMAX; ++g) {
+            const int v = th + kWG * g;
+            if (v < q.n) dst[v] = r[g];
+        }
+    }
+};
+
+template <typename T, int R, int C, int NVG>
+struct TileStage {
+    using Cfg = StreamCfg<T, R, C, NVG>;
+    Range16 qv, qm, qc, qp;
+    RegStage<Cfg::NV> rv;
+    RegStage<Cfg::NM> rm;
+    RegStage<Cfg::NC> rc;
+    RegStage<Cfg::NP> rp;
+
+    // All NV + NM + NC + NP loads, unconditionally (vectors past a range read
+    // zeros): a fixed count keeps the compiler's in-order load counters
+    // exact, so waiting for later loads of the current tile never waits for
+    // this prefetch.
+    __device__ __forceinline__ void issue(int p0, int p1, int b0, int b1, int v0, int v1,
+                                          const T *val, const void *masks, const int32_t *blk_col,
+                                          const int32_t *blk_ptr) {
+        qv = range16(val, (int64_t)v0 * (int64_t)sizeof(T), (int64_t)v1 * (int64_t)sizeof(T));
+        qm = range16(masks, (int64_t)b0 * R * Cfg::MB, (int64_t)b1 * R * Cfg::MB);
+        qc = range16(blk_col, (int64_t)b0 * 4, (int64_t)b1 * 4);
+        qp = range16(blk_ptr, (int64_t)p0 * 4, (int64_t)(p1 + 1) * 4);
+        fixed(rv, qv);
+        fixed(rm, qm);
+        fixed(rc, qc);
+        fixed(rp, qp);
+    }
+    template <int N>
+    __device__ __forceinline__ static void fixed(RegStage<N> &st, const Range16 &q) {
+        const uint32_t th16 = (uint32_t)threadIdx.x * 16u;
+#pragma unroll
+        for (int g = 0; g < N; ++g) st.r[g] = buf_load16(q.buf, th16 + (uint32_t)(kWG * 16 * g));
+    }
+};
+
+// Row sums of a value-mode tile.  Rows are contiguous value ranges
+// (range(row, vs, ve)); rows of at most kShortRow values are summed by one
+// thread each, longer ones are queued in LDS and summed by whole wavefronts
+// (lane-strided, then a butterfly), so one long row no longer holds up the
+// tile.  Each row is summed in a fixed order: results are reproducible.
+// term(v, acc) adds value slot v into acc[0..K); emit(row, acc) stores.
+// *s_nlong must be zero at entry (the caller clears it between barriers).
+constexpr int kShortRow = 32;
+
+template <typename T, int K, typename Range, typename Term, typename Emit>
+__device__ __forceinline__ void value_rows(int np, Range range, Term term, Emit emit,
+                                           int *s_long, int *s_nlong) {
+    const int th = threadIdx.x, lane = lane_id(), wv = th / kWave;
+    if (th < np) {
+        int vs, ve;
+        range(th, vs, ve);
+        if (ve - vs <= kShortRow) {
+            T acc[K];
+#pragma unroll
+            for (int q = 0; q < K; ++q) acc[q] = T(0);
+            for (int v = vs; v < ve; ++v) term(v, acc);
+            emit(th, acc);
+        } else {
+            s_long[atomicAdd(s_nlong, 1)] = th;
+        }
+    }
+    __syncthreads();
+    const int nl = *s_nlong;
+    for (int q0 = wv; q0 < nl; q0 += kWG / kWave) {
+        const int row = s_long[q0];
+        int vs, ve;
+        range(row, vs, ve);
+        T acc[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] = T(0);
+        for (int v = vs + lane; v < ve; v += kWave) term(v, acc);
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+            for (int d = 1; d < kWave; d <<= 1) acc[q] += __shfl_xor(acc[q], d);
+        if (lane == 0) emit(row, acc);
+    }
+}
+
+// Bounds of staged tile t: piece flag, panel range [p0,p1), block range
+// [b0,b1), value range [v0,v1).  A piece tile covers one panel.
+struct TileBounds {
+    int f, p0, p1, b0, b1, v0, v1;
+};
+
+__device__ __forceinline__ TileBounds tile_bounds(int64_t t, const int32_t *tp, const int32_t *tb,
+                                                  const int32_t *tv, const int32_t *tf) {
+    TileBounds b;
+    b.f = tf[t];
+    b.p0 = tp[t];
+    b.p1 = b.f ? b.p0 + 1 : tp[t + 1];
+    b.b0 = tb[t];
+    b.b1 = tb[t + 1];
+    b.v0 = tv[t];
+    b.v1 = tv[t + 1];
+    return b;
+}
+
+}  // namespace spc5

@@ -29,6 +29,7 @@
 // partial row sums are added in tile order by a small fixup kernel.  No
 // atomics: results are reproducible bit for bit.
 #include "spc5_internal.h"
+#include "stage.h"
 #include "wave.h"
 
 #include <algorithm>
@@ -36,32 +37,6 @@
 #include <cstdlib>
 
 namespace spc5 {
-
-constexpr int kWG = 256;   // threads per workgroup (4 wavefronts)
-
-template <typename T, int R, int C, int NVG = 4>
-struct StreamCfg {
-    using MT = typename MaskOf<C>::type;
-    static constexpr int MB = (int)sizeof(MT);
-    // LDS bytes for the values of one tile: NVG 16-byte vectors per thread
-    static constexpr int VBYTES = 4096 * NVG;
-    static constexpr int VT = (16384 - 16) / (int)sizeof(T);           // schedule cap
-    static constexpr int BT0 = 8192 / (C * (int)sizeof(T));
-    // blocks per tile: bounded by the x windows in LDS (C per block); beta(1,c)
-    // keeps no windows (value mode) and gives each thread BPT blocks
-    static constexpr int BPT = R == 1 ? 4 : 1;
-    static constexpr int BT = R == 1 ? kWG * BPT : (BT0 < 256 ? BT0 : 256);
-    static constexpr int PPW = kWG / R;                                // panels per tile
-    static constexpr int VVEC = VBYTES / 16;
-    static constexpr int MVEC = (BT * R * MB + 30) / 16;
-    static constexpr int CVEC = (BT * 4 + 30) / 16;
-    static constexpr int PVEC = ((PPW + 1) * 4 + 30) / 16;
-    static constexpr int NV = VVEC / kWG;                              // vectors per thread
-    static constexpr int NM = (MVEC + kWG - 1) / kWG;
-    static constexpr int NC = (CVEC + kWG - 1) / kWG;
-    static constexpr int NP = (PVEC + kWG - 1) / kWG;
-    static constexpr int U = R * C <= 16 ? 4 : 2;                      // blocks per step
-};
 
 // Tile capacities for a matrix (must match StreamCfg).
 void staged_caps(const spc5_matrix *A, int *vt, int *bt, int *ppw) {
@@ -71,127 +46,6 @@ void staged_caps(const spc5_matrix *A, int *vt, int *bt, int *ppw) {
     *bt = A->r == 1 ? 4 * kWG : std::min(256, 8192 / (cm * sz));
     *ppw = kWG / A->r;
 }
-
-// Kernel variants for the paper's ablations (spc5_set_variant).
-constexpr int kVarPartialX = 1;    // each row loads its own x (Section 3.1)
-constexpr int kVarRowReduce = 2;   // per-row sums of the sub-lanes (Section 3.2)
-
-// Row masks of block t in LDS (bytes of block t start at t*R*MB): the mask of
-// row i, the popcount of the rows below i and of the whole block.
-template <int R, int C>
-__device__ __forceinline__ void lds_block_masks(const uint8_t *sm, int t, int i, unsigned &m,
-                                                int &pre, int &tot) {
-    using MT = typename MaskOf<C>::type;
-    constexpr int MB = (int)sizeof(MT);
-    constexpr int WB = R * MB;
-    if constexpr (WB == 1 || WB == 2 || WB == 4 || WB == 8) {
-        uint64_t w;
-        if constexpr (WB == 1) w = sm[t];
-        else if constexpr (WB == 2) w = *(const uint16_t *)(sm + 2 * t);
-        else if constexpr (WB == 4) w = *(const uint32_t *)(sm + 4 * t);
-        else w = *(const uint64_t *)(sm + 8 * t);
-        const int sh = i * 8 * MB;
-        m = (unsigned)(w >> sh) & ((1u << (8 * MB)) - 1u);
-        pre = __popcll(sh ? (w & ((1ull << sh) - 1ull)) : 0ull);
-        tot = __popcll(w);
-    } else {
-        m = 0;
-        pre = 0;
-        tot = 0;
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
-            unsigned mr;
-            if constexpr (MB == 1) mr = sm[t * R + rr];
-            else mr = ((const uint16_t *)sm)[t * R + rr];
-            const int pc = __popc(mr);
-            pre += rr < i ? pc : 0;
-            m = rr == i ? mr : m;
-            tot += pc;
-        }
-    }
-}
-
-// Union of the r row masks of block t (the columns the block touches).
-template <int R, int C>
-__device__ __forceinline__ unsigned lds_block_union(const uint8_t *sm, int t) {
-    using MT = typename MaskOf<C>::type;
-    constexpr int MB = (int)sizeof(MT);
-    unsigned u = 0;
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) {
-        if constexpr (MB == 1) u |= sm[t * R + rr];
-        else u |= ((const uint16_t *)sm)[t * R + rr];
-    }
-    return u;
-}
-
-// A contiguous byte range of global memory, as 16-byte vectors from an
-// aligned base, addressed through a raw buffer descriptor whose record count
-// is the range's length: vector indices past the range read zeros, so the
-// staging loads need no clamping.
-struct Range16 {
-    Buf buf;
-    int n;       // vectors
-    int skew;    // bytes from the aligned base to the first wanted byte
-};
-
-__device__ __forceinline__ Range16 range16(const void *base, int64_t byte0, int64_t byte1) {
-    const int64_t a0 = byte0 & ~(int64_t)15;
-    Range16 r;
-    r.n = byte1 > byte0 ? (int)((byte1 - a0 + 15) >> 4) : 0;
-    r.skew = (int)(byte0 - a0);
-    r.buf = make_buf((const char *)base + a0, (int64_t)r.n * 16);
-    return r;
-}
-
-// Register stage of up to NVMAX vectors per thread and the matching LDS
-// stores.
-template <int NVMAX>
-struct RegStage {
-    v4u r[NVMAX];
-
-    __device__ __forceinline__ void commit(v4u *dst, const Range16 &q) const {
-        const int th = threadIdx.x;
-#pragma unroll
-        for (int g = 0; g < NVMAX; ++g) {
-            const int v = th + kWG * g;
-            if (v < q.n) dst[v] = r[g];
-        }
-    }
-};
-
-template <typename T, int R, int C, int NVG>
-struct TileStage {
-    using Cfg = StreamCfg<T, R, C, NVG>;
-    Range16 qv, qm, qc, qp;
-    RegStage<Cfg::NV> rv;
-    RegStage<Cfg::NM> rm;
-    RegStage<Cfg::NC> rc;
-    RegStage<Cfg::NP> rp;
-
-    // All NV + NM + NC + NP loads, unconditionally (vectors past a range read
-    // zeros): a fixed count keeps the compiler's in-order load counters
-    // exact, so waiting for later loads of the current tile never waits for
-    // this prefetch.
-    __device__ __forceinline__ void issue(int p0, int p1, int b0, int b1, int v0, int v1,
-                                          const T *val, const void *masks, const int32_t *blk_col,
-                                          const int32_t *blk_ptr) {
-        qv = range16(val, (int64_t)v0 * (int64_t)sizeof(T), (int64_t)v1 * (int64_t)sizeof(T));
-        qm = range16(masks, (int64_t)b0 * R * Cfg::MB, (int64_t)b1 * R * Cfg::MB);
-        qc = range16(blk_col, (int64_t)b0 * 4, (int64_t)b1 * 4);
-        qp = range16(blk_ptr, (int64_t)p0 * 4, (int64_t)(p1 + 1) * 4);
-        fixed(rv, qv);
-        fixed(rm, qm);
-        fixed(rc, qc);
-        fixed(rp, qp);
-    }
-    template <int N>
-    __device__ __forceinline__ static void fixed(RegStage<N> &st, const Range16 &q) {
-        const uint32_t th16 = (uint32_t)threadIdx.x * 16u;
-#pragma unroll
-        for (int g = 0; g < N; ++g) st.r[g] = buf_load16(q.buf, th16 + (uint32_t)(kWG * 16 * g));
-    }
-};
 
 // Rows phase of one staged tile: thread = (panel pl, sub-lane, row i) with S
 // sub-lanes per row (np*R*S <= 256 and S*R <= 64, so the butterfly stays in
@@ -459,6 +313,8 @@ __global__ __launch_bounds__(kWG) void k_spmv_vstream(
     __shared__ int s_vcol[VCAP];
     __shared__ int s_boff[BT + 1];
     __shared__ int s_wsum[kWG / kWave];
+    __shared__ int s_long[kWG];
+    __shared__ int s_nlong;
 
     const int th = threadIdx.x;
     const int lane = lane_id();
@@ -488,6 +344,7 @@ __global__ __launch_bounds__(kWG) void k_spmv_vstream(
         st.rc.commit(s_col, st.qc);
         st.rp.commit(s_bp, st.qp);
         st.rv.commit(s_val, st.qv);
+        if (th == 0) s_nlong = 0;
         const int skv = st.qv.skew, skm = st.qm.skew, skc = st.qc.skew, skp = st.qp.skew;
         __syncthreads();
         const MT *smk = (const MT *)((const uint8_t *)s_mask + skm);
@@ -556,23 +413,20 @@ __global__ __launch_bounds__(kWG) void k_spmv_vstream(
         }
         __syncthreads();
 
-        // rows: S sub-lanes per row over its contiguous products
-        int lgS = 0;
-        while (np * (2 << lgS) <= kWG && (2 << lgS) <= kWave) ++lgS;
-        const int S = 1 << lgS;
-        const int pl = th >> lgS, sub = th & (S - 1);
-        const bool live = pl < np;
-        const int bs = live ? max(sbp[pl], b0) - b0 : 0;
-        const int be = live ? min(sbp[pl + 1], b1) - b0 : 0;
-        const int vs = s_boff[bs], ve = s_boff[be];
-        T acc = T(0);
-        for (int v = vs + sub; v < ve; v += S) acc += sval[v];
-        for (int d = 1; d < S; d <<= 1) acc += __shfl_xor(acc, d);
-        if (live && sub == 0) {
-            const int64_t row = (int64_t)(p0 + pl);
-            if (f0) partial[t] = acc;              // summed by k_split_fixup
-            else if (row < nrows) y[row] = acc;
-        }
+        // rows: contiguous sums of the products
+        value_rows<T, 1>(
+            np,
+            [&](int pl, int &vs, int &ve) {
+                vs = s_boff[max(sbp[pl], b0) - b0];
+                ve = s_boff[min(sbp[pl + 1], b1) - b0];
+            },
+            [&](int v, T *acc) { acc[0] += sval[v]; },
+            [&](int pl, const T *acc) {
+                const int64_t row = (int64_t)(p0 + pl);
+                if (f0) partial[t] = acc[0];        // summed by k_split_fixup
+                else if (row < nrows) y[row] = acc[0];
+            },
+            s_long, &s_nlong);
         f0 = g0; p0 = q0; p1 = q1; b0 = c0; b1 = c1; v0 = w0; v1 = w1;
     }
 }
@@ -697,16 +551,19 @@ void free_staged_schedule(spc5_matrix *A) {
     A->nsplit = 0;
 }
 
-int build_staged_schedule(spc5_matrix *A, int ppw_req) {
+int build_staged_schedule(spc5_matrix *A, int ppw_req, bool shrink) {
     free_staged_schedule(A);
     A->staged_ok = true;
     int vt, bt, ppw;
     staged_caps(A, &vt, &bt, &ppw);
     if (ppw_req > 0) ppw = std::min(ppw, ppw_req);
-    // small matrices: narrower tiles, so that there are about 2048 of them
-    // to spread over the 256 compute units
-    bt = (int)std::min<int64_t>(bt, std::max<int64_t>(32, A->nblocks / 2048));
-    vt = (int)std::min<int64_t>(vt, std::max<int64_t>(256, A->nnz / 2048));
+    // small matrices launched alone: narrower tiles, so that there are about
+    // 2048 of them to spread over the 256 compute units (a batch, which
+    // spreads many matrices, keeps full tiles)
+    if (shrink) {
+        bt = (int)std::min<int64_t>(bt, std::max<int64_t>(32, A->nblocks / 2048));
+        vt = (int)std::min<int64_t>(vt, std::max<int64_t>(256, A->nnz / 2048));
+    }
     A->sppt = ppw;
     A->max_tile_values = 0;
     if (A->npanels == 0) return SPC5_OK;

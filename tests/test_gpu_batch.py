@@ -79,6 +79,84 @@ def test_batch_parity(dtype, k, dev):
     B.free()
 
 
+R1_SHAPES = [(1, 8), (1, 16), (1, 4), (1, 3), (1, 12), (1, 5)]
+
+
+def r1_batch():
+    """beta(1,c) batch (value-mode tiles): the uneven matrices plus one with
+    hub rows of thousands of nonzeros (panels split over several tiles)."""
+    from test_gpu_parity import long_panel_matrix
+    return BATCH[:14] + [long_panel_matrix(29)]
+
+
+R1 = r1_batch()
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("k", [1, 3, 4, 16, 20, 64])
+def test_batch_value_mode_parity(dtype, k, dev):
+    S = spc5()
+    say(f"value-mode batch {len(R1)} matrices {dtype} k={k}")
+    mats = [S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols,
+                                  *R1_SHAPES[m % len(R1_SHAPES)], dtype) for m, A in enumerate(R1)]
+    assert mats[-1].info.split_panels > 0
+    B = S.Spc5Batch(mats)
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    rng = np.random.default_rng(200 + k)
+    Xh = [rng.uniform(-1, 1, (A.ncols, k)) for A in R1]
+    Ys = B.spmm([torch.tensor(X, dtype=tdt, device=dev) for X in Xh])
+    torch.cuda.synchronize()
+    for m, A in enumerate(R1):
+        Y = Ys[m].cpu().double().numpy()
+        if dtype == "float64":
+            ref = oracle.csr_spmm(A.rowptr, A.colidx, A.values, Xh[m])
+            assert oracle.rel_l2(Y, ref) <= 1e-14, (m, A.name)
+        else:
+            ref = oracle.csr_spmm(A.rowptr, A.colidx, A.values.astype(np.float32).astype(np.float64),
+                                  Xh[m].astype(np.float32).astype(np.float64))
+            assert oracle.rel_l2(Y, ref) <= 1e-6, (m, A.name)
+
+
+def test_batch_value_mode_graph_replay(dev):
+    S = spc5()
+    say("value-mode batch graph replays")
+    mats = [S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols,
+                                  *R1_SHAPES[m % len(R1_SHAPES)]) for m, A in enumerate(R1)]
+    B = S.Spc5Batch(mats)
+    k = 4
+    rng = np.random.default_rng(13)
+    Xs = [torch.tensor(rng.uniform(-1, 1, (A.ncols, k)), device=dev) for A in R1]
+    Ys = [torch.zeros((A.nrows, k), dtype=torch.float64, device=dev) for A in R1]
+    B.set_operands(Xs, Ys)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        B.run(side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        B.run(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for X in Xs:
+            X.copy_(torch.tensor(rng.uniform(-1, 1, tuple(X.shape)), device=dev))
+        for Y in Ys:
+            Y.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = [Y.clone() for Y in Ys]
+        for Y in Ys:
+            Y.fill_(float("nan"))
+        B.run()
+        torch.cuda.synchronize()
+        for m, A in enumerate(R1):
+            assert torch.equal(got[m], Ys[m]), (rep, m)
+            ref = oracle.csr_spmm(A.rowptr, A.colidx, A.values, Xs[m].cpu().numpy())
+            assert oracle.rel_l2(got[m].cpu().numpy(), ref) <= 1e-14, (rep, m)
+
+
 def test_batch_rebind_smaller(dev):
     """A second binding with fewer right-hand sides and other vectors."""
     S = spc5()
