@@ -160,9 +160,10 @@ struct TileStage {
 };
 
 // Row sums of a value-mode tile.  Rows are contiguous value ranges
-// (range(row, vs, ve)); rows of at most kShortRow values are summed by one
-// thread each, longer ones are queued in LDS and summed by whole wavefronts
-// (lane-strided, then a butterfly), so one long row no longer holds up the
+// (range(row, vs, ve)).  Every row gets S sub-lanes (S the largest power of
+// two with np*S <= 256, at most 64) that stride its values and meet in a
+// butterfly; a row longer than S*kShortRow values is instead queued in LDS
+// and summed by a whole wavefront, so one long row no longer holds up the
 // tile.  Each row is summed in a fixed order: results are reproducible.
 // term(v, acc) adds value slot v into acc[0..K); emit(row, acc) stores.
 // *s_nlong must be zero at entry (the caller clears it between barriers).
@@ -172,33 +173,38 @@ template <typename T, int K, typename Range, typename Term, typename Emit>
 __device__ __forceinline__ void value_rows(int np, Range range, Term term, Emit emit,
                                            int *s_long, int *s_nlong) {
     const int th = threadIdx.x, lane = lane_id(), wv = th / kWave;
-    if (th < np) {
-        int vs, ve;
-        range(th, vs, ve);
-        if (ve - vs <= kShortRow) {
-            T acc[K];
+    int lgS = 0;
+    while (np * (2 << lgS) <= kWG && (2 << lgS) <= kWave) ++lgS;
+    const int S = 1 << lgS;
+    const int pl = th >> lgS, sub = th & (S - 1);
+    const bool live = pl < np;
+    int vs = 0, ve = 0;
+    if (live) range(pl, vs, ve);
+    const bool lng = live && ve - vs > S * kShortRow;
+    T acc[K];
 #pragma unroll
-            for (int q = 0; q < K; ++q) acc[q] = T(0);
-            for (int v = vs; v < ve; ++v) term(v, acc);
-            emit(th, acc);
-        } else {
-            s_long[atomicAdd(s_nlong, 1)] = th;
-        }
-    }
+    for (int q = 0; q < K; ++q) acc[q] = T(0);
+    if (live && !lng)
+        for (int v = vs + sub; v < ve; v += S) term(v, acc);
+    if (lng && sub == 0) s_long[atomicAdd(s_nlong, 1)] = pl;
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+        for (int d = 1; d < S; d <<= 1) acc[q] += __shfl_xor(acc[q], d);
+    if (live && !lng && sub == 0) emit(pl, acc);
     __syncthreads();
     const int nl = *s_nlong;
     for (int q0 = wv; q0 < nl; q0 += kWG / kWave) {
         const int row = s_long[q0];
-        int vs, ve;
-        range(row, vs, ve);
-        T acc[K];
+        int rs, re;
+        range(row, rs, re);
+        T a[K];
 #pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] = T(0);
-        for (int v = vs + lane; v < ve; v += kWave) term(v, acc);
+        for (int q = 0; q < K; ++q) a[q] = T(0);
+        for (int v = rs + lane; v < re; v += kWave) term(v, a);
 #pragma unroll
         for (int q = 0; q < K; ++q)
-            for (int d = 1; d < kWave; d <<= 1) acc[q] += __shfl_xor(acc[q], d);
-        if (lane == 0) emit(row, acc);
+            for (int d = 1; d < kWave; d <<= 1) a[q] += __shfl_xor(a[q], d);
+        if (lane == 0) emit(row, a);
     }
 }
 

@@ -346,7 +346,8 @@ def test_transpose(A, rc, dev):
 
 @pytest.mark.parametrize("A", CASES, ids=lambda a: a.name)
 @pytest.mark.parametrize("rc,trc", [((1, 8), (0, 0)), ((2, 4), (0, 0)), ((4, 4), (0, 0)),
-                                    ((3, 5), (4, 4)), ((8, 16), (1, 8)), ((4, 4), (2, 8))],
+                                    ((3, 5), (4, 4)), ((8, 16), (1, 8)), ((4, 4), (2, 8)),
+                                    ((4, 4), (3, 5)), ((1, 16), (8, 8))],
                          ids=lambda t: "b%d_%d" % t)
 def test_transpose_plan(A, rc, trc, dev):
     """x_bar = A^T y_bar through the stored A^T (forward kernel, no atomics):
