@@ -35,8 +35,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SpMV GFLOP/s + achieved HBM GB/s (% peak), SPC5 vs CSR, fwd+bwd, FP64/FP32"
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2307_14774_amd/csrc/staged.hip", "paper_2307_14774_amd/csrc/spmv.hip",
-                  "paper_2307_14774_amd/csrc/wave.h", "paper_2307_14774_amd/csrc/tile.h"]
+KERNEL_SOURCES = ["paper_2307_14774_amd/csrc/staged.hip", "paper_2307_14774_amd/csrc/stage.h",
+                  "paper_2307_14774_amd/csrc/spmv.hip", "paper_2307_14774_amd/csrc/wave.h",
+                  "paper_2307_14774_amd/csrc/tile.h"]
 FWD_KERNEL = "k_spmv_stream"
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_spc5_fwd.json")
 COPY_ELEMS = 1 << 27          # calibration copy: 1 GiB read + 1 GiB written (float64)

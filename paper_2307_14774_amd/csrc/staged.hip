@@ -222,15 +222,15 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
         const int tb = has ? th : 0;
         const unsigned un = has ? lds_block_union<R, C>(smb, tb) : 0u;
         const int col0 = has ? scol[tb] : 0;
+        // The whole window x[anchor .. anchor+C) in 16-byte loads: the buffer
+        // range check is per dword, so a window running past the last column
+        // reads zeros there, and blocks whose rows use no column read nothing.
         T xw[C];
+        if constexpr (VAR & kVarPartialX) {
 #pragma unroll
-        for (int k = 0; k < C; ++k) {
-            if constexpr (VAR & kVarPartialX)
-                xw[k] = T(0);   // no shared x windows: rows load their own
-            else
-                xw[k] = buf_load<T>(xbuf, ((un >> k) & 1u)
-                                              ? (uint32_t)(col0 + k) * (uint32_t)sizeof(T)
-                                              : kOOB);
+            for (int k = 0; k < C; ++k) xw[k] = T(0);   // rows load their own x
+        } else {
+            load_window<T, C>(xbuf, un ? (uint32_t)col0 * (uint32_t)sizeof(T) : kOOB, xw);
         }
         // ... then the next tile's staging loads, so both are in flight
         // together and waiting for the gathers does not wait for them (the
