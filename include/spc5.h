@@ -190,20 +190,22 @@ int spc5_spmv_values(const spc5_matrix *A, const void *values, const void *x,
  * the stream first); the accumulation order varies between runs.
  * With a plan (spc5_prepare_transpose): the forward kernel over the stored
  * A^T; no atomics, the result is reproducible bit for bit.  When `values` is
- * given, the plan first moves them to A^T's order in a buffer owned by A, so
- * such calls on one handle must not overlap in time (one stream, or
- * synchronised streams). */
+ * given, the plan first moves them to A^T's order (two passes through
+ * buffers owned by A: a scatter into staging slots grouped by position in
+ * A^T, then a gather inside each group), so such calls on one handle must
+ * not overlap in time (one stream, or synchronised streams). */
 int spc5_spmv_transpose(const spc5_matrix *A, const void *ybar, void *xbar,
                         void *stream);
 int spc5_spmv_transpose_values(const spc5_matrix *A, const void *values,
                                const void *ybar, void *xbar, void *stream);
 
 /* Build the transposed-product plan of A: A^T converted on the device to
- * SPC5 beta(r,c) storage (r = c = 0: A's own shape) plus, for each of its
- * packed values, the packed index of the same entry in A.  Afterwards
- * spc5_spmv_transpose* run as a forward product over A^T.  Costs about the
- * device memory of A once more (values twice: A^T's own and the gather
- * buffer) plus 4 bytes per nonzero; held until spc5_free.  Synchronous.
+ * SPC5 beta(r,c) storage (r = c = 0: A's own shape) plus the two index
+ * arrays that move caller values from A's packed order to A^T's.
+ * Afterwards spc5_spmv_transpose* run as a forward product over A^T.  Costs
+ * about the device memory of A once more, plus two more value arrays (the
+ * staging and the moved values) and 8 bytes per nonzero (the two index
+ * arrays); held until spc5_free.  Synchronous.
  * Calling it again with the same shape is a no-op.
  * Errors: SPC5_EINVAL (NULL A, a plan with another shape exists),
  * SPC5_EUNSUPPORTED (r or c out of range, A^T's block count >= 2^31),

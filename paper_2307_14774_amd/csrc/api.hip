@@ -153,8 +153,8 @@ void free_matrix(spc5_matrix *A) {
     if (!A) return;
     DeviceGuard g(A->device);
     free_matrix(A->tr);
-    if (A->tr_perm) (void)hipFree(A->tr_perm);
-    if (A->tr_vals) (void)hipFree(A->tr_vals);
+    for (void *p : {(void *)A->tr_scatter, (void *)A->tr_gather, A->tr_stage, A->tr_vals})
+        if (p) (void)hipFree(p);
     if (A->blk_ptr) (void)hipFree(A->blk_ptr);
     if (A->blk_col) (void)hipFree(A->blk_col);
     if (A->masks) (void)hipFree(A->masks);

@@ -119,10 +119,14 @@ struct BatchFix {
     int32_t mat, row, t0, t1;
 };
 
+// 16-byte value vectors per thread of a value-mode tile: kValueTile values,
+// the cap of the batch-private schedules.
+template <typename T> constexpr int kBatchNVG = kValueTile * (int)sizeof(T) / 4096;
+
 // Shared memory of one value-mode tile (sized for the widest mask type).
 template <typename T>
 struct VTileLds {
-    using Cfg = StreamCfg<T, 1, 16, 4>;
+    using Cfg = StreamCfg<T, 1, 16, kBatchNVG<T>>;
     static constexpr int VCAP = Cfg::VVEC * 16 / (int)sizeof(T);
     v4u val[Cfg::VVEC];
     v4u mask[Cfg::MVEC];
@@ -139,7 +143,7 @@ struct VTileLds {
 // (1 for c <= 8, 2 above); register counts are those of the widest case.
 template <typename T>
 struct BStage {
-    using Cfg = StreamCfg<T, 1, 16, 4>;
+    using Cfg = StreamCfg<T, 1, 16, kBatchNVG<T>>;
     Range16 qv, qm, qc, qp;
     RegStage<Cfg::NV> rv;
     RegStage<Cfg::NM> rm;
@@ -230,7 +234,7 @@ __global__ __launch_bounds__(kWG) void k_batch_v(const BatchDescV *__restrict__ 
     __shared__ unsigned s_w;
     constexpr int VCAP = VTileLds<T>::VCAP;
     constexpr int NX = (VCAP + kWG - 1) / kWG;
-    constexpr int BPT = StreamCfg<T, 1, 16, 4>::BPT;
+    constexpr int BPT = StreamCfg<T, 1, 16, kBatchNVG<T>>::BPT;
     const int th = threadIdx.x;
     const int lane = lane_id();
     const int wv = th / kWave;
@@ -592,6 +596,11 @@ int spc5_batch_create(int nmat, spc5_matrix *const *mats, spc5_batch **out) {
             if (st != SPC5_OK) {
                 spc5_batch_free(B);
                 return st;
+            }
+            const int sz = A->dtype == SPC5_F64 ? 8 : 4;
+            if ((int64_t)S.max_tile_values * sz + 16 > (int64_t)kValueTile * sz) {
+                spc5_batch_free(B);
+                return fail(SPC5_EUNSUPPORTED, "batch tile exceeds its LDS value buffer");
             }
         }
     }

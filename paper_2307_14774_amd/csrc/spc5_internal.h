@@ -33,11 +33,15 @@ struct spc5_matrix {
     int32_t *split_p = nullptr, *split_t0 = nullptr, *split_t1 = nullptr;   // [nsplit]
     int64_t nsplit = 0;
     void *partial = nullptr;       // [ntiles_staged * r] partial row sums of pieces
-    // transposed-product plan (spc5_prepare_transpose): A^T in beta(r,c) and,
-    // for each of its packed values, the packed index of the same entry in A
+    // transposed-product plan (spc5_prepare_transpose): A^T in beta(r,c) and
+    // the two passes that move caller values from A's packed order to
+    // A^T's: a scatter into staging slots grouped by output bucket, then a
+    // gather inside each bucket (see transpose_plan.hip)
     spc5_matrix *tr = nullptr;
-    int32_t *tr_perm = nullptr;    // [nnz]
-    void *tr_vals = nullptr;       // [nnz] gather buffer for caller values
+    int32_t *tr_scatter = nullptr; // [nnz] staging slot of A's packed value p
+    int32_t *tr_gather = nullptr;  // [nnz] staging slot read for A^T's value q
+    void *tr_stage = nullptr;      // [nnz] staging buffer
+    void *tr_vals = nullptr;       // [nnz] caller values in A^T's packed order
 };
 
 struct spc5_csr {
@@ -77,8 +81,10 @@ hipError_t launch_spmv(const spc5_matrix *A, const void *val, const void *x, voi
 hipError_t launch_spmv_staged(const spc5_matrix *A, const void *val, const void *x, void *y,
                               hipStream_t s, int remap);
 // (Re)build the staged kernel's tile schedule with at most ppw panels per tile
-// (0: as many as one workgroup has rows for).
-int build_staged_schedule(spc5_matrix *A, int ppw, bool shrink = true);
+// (0: as many as one workgroup has rows for), for a launch of the matrix
+// alone (small matrices: narrower tiles) or for the persistent batch kernel
+// (alone = false: full-size tiles).
+int build_staged_schedule(spc5_matrix *A, int ppw, bool alone = true);
 void free_staged_schedule(spc5_matrix *A);
 hipError_t excl_scan_i64(const int64_t *in, int64_t n, int64_t *out, hipStream_t s,
                          int64_t **scratch);

@@ -17,7 +17,6 @@ struct StreamCfg {
     static constexpr int MB = (int)sizeof(MT);
     // LDS bytes for the values of one tile: NVG 16-byte vectors per thread
     static constexpr int VBYTES = 4096 * NVG;
-    static constexpr int VT = (16384 - 16) / (int)sizeof(T);           // schedule cap
     static constexpr int BT0 = 8192 / (C * (int)sizeof(T));
     // blocks per tile: bounded by the x windows in LDS (C per block); beta(1,c)
     // keeps no windows (value mode) and gives each thread BPT blocks
@@ -34,6 +33,10 @@ struct StreamCfg {
     static constexpr int NP = (PVEC + kWG - 1) / kWG;
     static constexpr int U = R * C <= 16 ? 4 : 2;                      // blocks per step
 };
+
+// Values per value-mode (beta(1,c)) tile, 16 bytes of padding included: 8 KiB
+// of LDS in FP32, 16 KiB in FP64.
+constexpr int kValueTile = 2048;
 
 // Tile capacities for a matrix (must match StreamCfg).
 void staged_caps(const spc5_matrix *A, int *vt, int *bt, int *ppw);

@@ -42,7 +42,10 @@ namespace spc5 {
 void staged_caps(const spc5_matrix *A, int *vt, int *bt, int *ppw) {
     const int sz = A->dtype == SPC5_F64 ? 8 : 4;
     const int cm = A->c <= 4 ? 4 : (A->c <= 8 ? 8 : 16);
-    *vt = (16384 - 16) / sz;
+    // value mode keeps a second LDS array per value (its decoded column):
+    // about kValueTile values per tile keep enough workgroups per compute
+    // unit for the latency-bound per-nonzero gathers
+    *vt = ((A->r == 1 ? kValueTile * sz : 16384) - 16) / sz;
     *bt = A->r == 1 ? 4 * kWG : std::min(256, 8192 / (cm * sz));
     *ppw = kWG / A->r;
 }
@@ -437,7 +440,7 @@ __global__ __launch_bounds__(kWG) void k_spmv_vstream(
 // new tile when adding it would pass vt values or bt blocks.  A panel larger
 // than a whole tile is cut into pieces of at most vt values and bt blocks,
 // each a tile of its own flagged as a piece; the pieces' partial row sums
-// are added in tile order by k_split_fixup, so the result stays
+// are added in a fixed order by k_split_fixup, so the result stays
 // reproducible.  One thread per group; pass 0 counts the tiles and the split
 // panels of each group, pass 1 writes them.
 template <typename MT>
@@ -513,19 +516,25 @@ __global__ void k_tile_sentinel(int64_t npanels, int64_t ntiles, const int32_t *
     tf[ntiles] = 0;
 }
 
-// Rows of a split panel: the partial sums of its pieces, in tile order.
+// Rows of a split panel: the partial sums of its pieces.  One wavefront per
+// row (a hub row can have hundreds of pieces): lane l adds pieces l, l+64, ...
+// in tile order, then a butterfly; the order is fixed, so the result is
+// reproducible.
 template <typename T>
-__global__ void k_split_fixup(int64_t nsplit, int r, int64_t nrows, const int32_t *sp,
-                              const int32_t *st0, const int32_t *st1, const T *partial, T *y) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nsplit * r) return;
+__global__ __launch_bounds__(256) void k_split_fixup(int64_t nsplit, int r, int64_t nrows,
+                                                     const int32_t *sp, const int32_t *st0,
+                                                     const int32_t *st1, const T *partial, T *y) {
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (q >= nsplit * r) return;    // uniform over the wavefront
+    const int lane = lane_id();
     const int64_t s = q / r;
     const int i = (int)(q % r);
     const int64_t row = (int64_t)sp[s] * r + i;
     if (row >= nrows) return;
     T acc = T(0);
-    for (int64_t t = st0[s]; t <= st1[s]; ++t) acc += partial[t * r + i];
-    y[row] = acc;
+    for (int64_t t = st0[s] + lane; t <= st1[s]; t += kWave) acc += partial[t * r + i];
+    for (int d = 1; d < kWave; d <<= 1) acc += __shfl_xor(acc, d);
+    if (lane == 0) y[row] = acc;
 }
 
 template <typename MT>
@@ -551,7 +560,7 @@ void free_staged_schedule(spc5_matrix *A) {
     A->nsplit = 0;
 }
 
-int build_staged_schedule(spc5_matrix *A, int ppw_req, bool shrink) {
+int build_staged_schedule(spc5_matrix *A, int ppw_req, bool alone) {
     free_staged_schedule(A);
     A->staged_ok = true;
     int vt, bt, ppw;
@@ -560,7 +569,7 @@ int build_staged_schedule(spc5_matrix *A, int ppw_req, bool shrink) {
     // small matrices launched alone: narrower tiles, so that there are about
     // 2048 of them to spread over the 256 compute units (a batch, which
     // spreads many matrices, keeps full tiles)
-    if (shrink) {
+    if (alone) {
         bt = (int)std::min<int64_t>(bt, std::max<int64_t>(32, A->nblocks / 2048));
         vt = (int)std::min<int64_t>(vt, std::max<int64_t>(256, A->nnz / 2048));
     }
@@ -678,7 +687,7 @@ static hipError_t launch_stream_g(const spc5_matrix *A, const T *val, const T *x
                            (const typename MaskOf<C>::type *)A->masks, val, x, y,
                            (T *)A->partial);
     if (A->nsplit > 0) {
-        const int64_t n = A->nsplit * R;
+        const int64_t n = A->nsplit * R * kWave;    // a wavefront per row
         hipLaunchKernelGGL(k_split_fixup<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                            A->nsplit, R, A->nrows, A->split_p, A->split_t0, A->split_t1,
                            (const T *)A->partial, y);
@@ -698,14 +707,17 @@ static bool sparse_rows(const spc5_matrix *A) {
     return A->nblocks > 0 && 2.0 * (double)A->nnz < (double)A->nblocks * A->r * A->c;
 }
 
-// LDS value buffer sized to the largest tile of the matrix: 4, 8 or 16 KiB.
+// LDS value buffer sized to the largest tile of the matrix: 4, 8 or 16 KiB
+// (value-mode tiles at most kValueTile values).
 template <typename T, int R, int C, bool SPARSE>
 static hipError_t launch_stream_s(const spc5_matrix *A, const T *val, const T *x, T *y,
                                   hipStream_t s, int remap) {
     const int64_t need = (int64_t)A->max_tile_values * (int64_t)sizeof(T) + 16;
     if (need <= 4096) return launch_stream_g<T, R, C, 1, SPARSE>(A, val, x, y, s, remap);
     if (need <= 8192) return launch_stream_g<T, R, C, 2, SPARSE>(A, val, x, y, s, remap);
-    return launch_stream_g<T, R, C, 4, SPARSE>(A, val, x, y, s, remap);
+    // value-mode tiles stop at kValueTile values: 8 KiB in FP32
+    if constexpr (R == 1 && sizeof(T) == 4) return hipErrorInvalidValue;
+    else return launch_stream_g<T, R, C, 4, SPARSE>(A, val, x, y, s, remap);
 }
 
 template <typename T, int R, int C>

@@ -14,9 +14,18 @@
 //     disjoint and increasing, and a block lists its rows in order), so the
 //     result is A^T in CSR form with sorted column indices;
 //  3. convert that CSR to beta(r,c) with the ordinary conversion, placing
-//     A's values and, as an int32 payload, A's packed index of every entry
-//     (the permutation used to gather caller-supplied values theta).
+//     A's values and, as an int32 payload, A's packed index of every entry:
+//     the permutation perm (A^T's value q is A's value perm[q]);
+//  4. split perm for caller-supplied values theta.  A single gather
+//     theta[perm[q]] reads one scattered word per cache line (perm jumps
+//     across all of A for every row of A^T).  Instead A^T's packed order is
+//     cut into buckets of kPermBucket consecutive values, A's values are
+//     scattered into staging slots grouped by bucket (slot order inside a
+//     bucket: A's packed order), and each bucket is then gathered from its
+//     own slots -- reads coalesced in the first pass, each bucket's window
+//     small enough to stay in L2 in the second.
 #include "spc5_internal.h"
+#include "wave.h"
 
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/iterator/counting_iterator.hpp>
@@ -73,13 +82,75 @@ __global__ void k_gather_csr(int64_t nnz, const int32_t *__restrict__ idx,
     val_t[i] = val[k];
 }
 
-// out[q] = in[perm[q]]: caller values moved to A^T's packed order.
+// Values of A^T per bucket of the two-pass value move: the staging window of
+// a bucket (512 KiB in FP32) stays in L2 while its outputs are gathered.
+constexpr int64_t kPermBucket = 131072;
+
+// key[perm[q]] = bucket of q: for every packed value of A, the bucket of its
+// position in A^T.
+__global__ void k_bucket_keys(int64_t nnz, const int32_t *__restrict__ perm,
+                              int32_t *__restrict__ key) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz) key[perm[q]] = (int32_t)(q / kPermBucket);
+}
+
+// slot[order[t]] = t: the staging slot of each value of A.
+__global__ void k_invert(int64_t nnz, const int32_t *__restrict__ order,
+                         int32_t *__restrict__ slot) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nnz) slot[order[t]] = (int32_t)t;
+}
+
+// perm[q] <- slot[perm[q]] (in place): the staging slot holding A^T's value q.
+__global__ void k_compose(int64_t nnz, const int32_t *__restrict__ slot,
+                          int32_t *__restrict__ perm) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nnz) perm[q] = slot[perm[q]];
+}
+
+// Pass 1: stage[slot[i]] = in[i].  Each workgroup moves a contiguous chunk of
+// kMoveChunk values of A, so its writes into one bucket's slots form one
+// contiguous run (about kMoveChunk / number of buckets values) that a single
+// L2 assembles into whole lines.
+constexpr int64_t kMoveChunk = 16384;
+
 template <typename T>
-__global__ void k_permute(int64_t n, const int32_t *__restrict__ perm, const T *__restrict__ in,
-                          T *__restrict__ out) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
-        out[q] = in[perm[q]];
+__global__ __launch_bounds__(256) void k_stage_scatter(int64_t n, const int32_t *__restrict__ slot,
+                                                       const T *__restrict__ in,
+                                                       T *__restrict__ stage) {
+    const int64_t i0 = (int64_t)blockIdx.x * kMoveChunk;
+    const int64_t i1 = min(i0 + kMoveChunk, n);
+#pragma unroll 8
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) stage[slot[i]] = in[i];
+}
+
+// Pass 2: out[q] = stage[src[q]], src[q] inside q's bucket.  Workgroups reach
+// the kXcds XCDs round robin; XCD x gathers buckets x, x + kXcds, ... and its
+// kGatherPerXcd workgroups split each bucket, so an XCD's L2 holds one
+// bucket's window at a time.
+constexpr int kGatherPerXcd = 128;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_stage_gather(int64_t n, const int32_t *__restrict__ src,
+                                                      const T *__restrict__ stage,
+                                                      T *__restrict__ out) {
+    constexpr int64_t share = kPermBucket / kGatherPerXcd;
+    const int x = (int)(blockIdx.x % kXcds), j = (int)(blockIdx.x / kXcds);
+    const int64_t nb = (n + kPermBucket - 1) / kPermBucket;
+    for (int64_t b = x; b < nb; b += kXcds) {
+        const int64_t q0 = b * kPermBucket + j * share;
+        const int64_t q1 = min(q0 + share, n);
+        for (int64_t q = q0 + threadIdx.x; q < q1; q += 256) out[q] = stage[src[q]];
+    }
+}
+
+template <typename T>
+static void launch_move(const spc5_matrix *A, const T *vals, hipStream_t s) {
+    const int64_t n = A->nnz;
+    hipLaunchKernelGGL(k_stage_scatter<T>, dim3((unsigned)((n + kMoveChunk - 1) / kMoveChunk)),
+                       dim3(256), 0, s, n, A->tr_scatter, vals, (T *)A->tr_stage);
+    hipLaunchKernelGGL(k_stage_gather<T>, dim3(kXcds * kGatherPerXcd), dim3(256), 0, s, n,
+                       A->tr_gather, (const T *)A->tr_stage, (T *)A->tr_vals);
 }
 
 int build_transpose_plan(spc5_matrix *A, int r, int c) {
@@ -92,8 +163,9 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     int64_t *rowptr_t = nullptr;
     void *val_t = nullptr, *tmp = nullptr;
     spc5_matrix *T = nullptr;
-    int32_t *perm = nullptr;
-    void *gbuf = nullptr;
+    int32_t *perm = nullptr, *scat = nullptr;
+    void *gbuf = nullptr, *stage = nullptr;
+    size_t tmp_bytes = 0;
     auto cleanup = [&]() {
         for (void *p : {(void *)row_of, (void *)col_of, (void *)key_s, (void *)idx_s,
                         (void *)colidx_t, (void *)rowptr_t, val_t, tmp})
@@ -102,8 +174,8 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     auto fail_all = [&](int st) {
         cleanup();
         free_matrix(T);
-        if (perm) (void)hipFree(perm);
-        if (gbuf) (void)hipFree(gbuf);
+        for (void *p : {(void *)perm, (void *)scat, gbuf, stage})
+            if (p) (void)hipFree(p);
         return st;
     };
     const size_t nz = (size_t)std::max<int64_t>(nnz, 1);
@@ -134,7 +206,6 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     if (nnz > 0) {
         unsigned bits = 1;
         while (bits < 31 && ((int64_t)1 << bits) < A->ncols) ++bits;
-        size_t tmp_bytes = 0;
         rocprim::counting_iterator<int32_t> iota(0);
         if ((e = rocprim::radix_sort_pairs(nullptr, tmp_bytes, col_of, key_s, iota, idx_s,
                                            (size_t)nnz, 0u, bits, s)) != hipSuccess ||
@@ -174,9 +245,42 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     int st = convert_on_device(T, rowptr_t, colidx_t, val_t, idx_s, perm);
     if (st != SPC5_OK) return fail_all(st);
     if ((st = finish_matrix(T)) != SPC5_OK) return fail_all(st);
+    // 4. staging slots: a stable sort of A's packed indices by the bucket of
+    // their A^T position (row_of, col_of and key_s are free again)
+    if ((e = hipMalloc((void **)&scat, nz * 4)) != hipSuccess ||
+        (e = hipMalloc(&stage, nz * vb + kPad)) != hipSuccess)
+        return fail_all(hip_fail(e, "allocating the transpose plan"));
+    if (nnz > 0) {
+        const unsigned grid = (unsigned)((nnz + 255) / 256);
+        hipLaunchKernelGGL(k_bucket_keys, dim3(grid), dim3(256), 0, s, nnz, perm, row_of);
+        const int64_t nb = (nnz + kPermBucket - 1) / kPermBucket;
+        unsigned bits = 1;
+        while (bits < 31 && ((int64_t)1 << bits) < nb) ++bits;
+        size_t need = 0;
+        rocprim::counting_iterator<int32_t> iota(0);
+        if ((e = rocprim::radix_sort_pairs(nullptr, need, row_of, col_of, iota, key_s,
+                                           (size_t)nnz, 0u, bits, s)) != hipSuccess)
+            return fail_all(hip_fail(e, "sorting by bucket"));
+        if (need > tmp_bytes) {
+            if (tmp) (void)hipFree(tmp);
+            tmp = nullptr;
+            if ((e = hipMalloc(&tmp, need)) != hipSuccess)
+                return fail_all(hip_fail(e, "allocating the transpose plan"));
+            tmp_bytes = need;
+        }
+        if ((e = rocprim::radix_sort_pairs(tmp, need, row_of, col_of, iota, key_s, (size_t)nnz,
+                                           0u, bits, s)) != hipSuccess)
+            return fail_all(hip_fail(e, "sorting by bucket"));
+        hipLaunchKernelGGL(k_invert, dim3(grid), dim3(256), 0, s, nnz, key_s, scat);
+        hipLaunchKernelGGL(k_compose, dim3(grid), dim3(256), 0, s, nnz, scat, perm);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return fail_all(hip_fail(e, "building the staging slots"));
+    }
     cleanup();
     A->tr = T;
-    A->tr_perm = perm;
+    A->tr_scatter = scat;
+    A->tr_gather = perm;
+    A->tr_stage = stage;
     A->tr_vals = gbuf;
     return SPC5_OK;
 }
@@ -187,13 +291,8 @@ hipError_t launch_transpose_plan(const spc5_matrix *A, const void *vals, const v
     const void *tv = T->val;
     if (vals && A->nnz > 0) {
         // the caller's values (A's packed order) moved to A^T's packed order
-        const unsigned grid = (unsigned)std::min<int64_t>((A->nnz + 255) / 256, 8192);
-        if (A->dtype == SPC5_F64)
-            hipLaunchKernelGGL(k_permute<double>, dim3(grid), dim3(256), 0, s, A->nnz,
-                               A->tr_perm, (const double *)vals, (double *)A->tr_vals);
-        else
-            hipLaunchKernelGGL(k_permute<float>, dim3(grid), dim3(256), 0, s, A->nnz,
-                               A->tr_perm, (const float *)vals, (float *)A->tr_vals);
+        if (A->dtype == SPC5_F64) launch_move<double>(A, (const double *)vals, s);
+        else launch_move<float>(A, (const float *)vals, s);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         tv = A->tr_vals;
