@@ -326,7 +326,7 @@ def backward_extras(dev):
 
 
 def batch_extras(dev, nmat=256, ks=(1, 4, 16)):
-    """NEXT-3 workload: `nmat` uneven matrices (log-uniform 1k..200k rows,
+    """Batched workload: `nmat` uneven matrices (log-uniform 1k..200k rows,
     Zipf(1.5) row lengths capped at 512, 30% of nonzeros in runs), beta(r,c)
     per matrix from the byte-model autotuner, k right-hand sides, all in one
     persistent launch; against plain FP64 single SpMVs (CSR kernel and
