@@ -153,7 +153,8 @@ void free_matrix(spc5_matrix *A) {
     if (!A) return;
     DeviceGuard g(A->device);
     free_matrix(A->tr);
-    for (void *p : {(void *)A->tr_scatter, (void *)A->tr_gather, A->tr_stage, A->tr_vals})
+    for (void *p : {(void *)A->tr_lidx, (void *)A->tr_gpos, (void *)A->tr_src, A->tr_stage,
+                    A->tr_vals})
         if (p) (void)hipFree(p);
     if (A->blk_ptr) (void)hipFree(A->blk_ptr);
     if (A->blk_col) (void)hipFree(A->blk_col);

@@ -34,12 +34,12 @@ struct spc5_matrix {
     int64_t nsplit = 0;
     void *partial = nullptr;       // [ntiles_staged * r] partial row sums of pieces
     // transposed-product plan (spc5_prepare_transpose): A^T in beta(r,c) and
-    // the two passes that move caller values from A's packed order to
-    // A^T's: a scatter into staging slots grouped by output bucket, then a
-    // gather inside each bucket (see transpose_plan.hip)
+    // the tables of the two LDS passes that move caller values from A's
+    // packed order to A^T's (see transpose_plan.hip)
     spc5_matrix *tr = nullptr;
-    int32_t *tr_scatter = nullptr; // [nnz] staging slot of A's packed value p
-    int32_t *tr_gather = nullptr;  // [nnz] staging slot read for A^T's value q
+    uint16_t *tr_lidx = nullptr;   // [nnz] pass 1: chunk-local value to write
+    int32_t *tr_gpos = nullptr;    // [nnz] pass 1: staging slot written
+    uint16_t *tr_src = nullptr;    // [nnz] pass 2: bucket-local slot read
     void *tr_stage = nullptr;      // [nnz] staging buffer
     void *tr_vals = nullptr;       // [nnz] caller values in A^T's packed order
 };

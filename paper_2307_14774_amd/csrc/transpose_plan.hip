@@ -19,11 +19,14 @@
 //  4. split perm for caller-supplied values theta.  A single gather
 //     theta[perm[q]] reads one scattered word per cache line (perm jumps
 //     across all of A for every row of A^T).  Instead A^T's packed order is
-//     cut into buckets of kPermBucket consecutive values, A's values are
-//     scattered into staging slots grouped by bucket (slot order inside a
-//     bucket: A's packed order), and each bucket is then gathered from its
-//     own slots -- reads coalesced in the first pass, each bucket's window
-//     small enough to stay in L2 in the second.
+//     cut into buckets of W = 16384 values (one LDS window), A's values
+//     get staging slots grouped by bucket (inside a bucket: A's packed
+//     order), and two passes move them, each through LDS: pass 1 loads a
+//     contiguous chunk of W values of A into LDS and writes them out in slot
+//     order (one contiguous run per bucket); pass 2 loads one bucket's slots
+//     into LDS and writes the bucket's values of A^T in order.  Every global
+//     read and write is contiguous; the permutations happen in LDS, with
+//     16-bit local indices.
 #include "spc5_internal.h"
 #include "wave.h"
 
@@ -82,16 +85,17 @@ __global__ void k_gather_csr(int64_t nnz, const int32_t *__restrict__ idx,
     val_t[i] = val[k];
 }
 
-// Values of A^T per bucket of the two-pass value move: the staging window of
-// a bucket (512 KiB in FP32) stays in L2 while its outputs are gathered.
-constexpr int64_t kPermBucket = 131072;
+// Values per LDS window of the two-pass value move (128 KiB in FP64, 64 KiB
+// in FP32: two workgroups per compute unit), and threads per workgroup.
+constexpr int kMoveValues = 16384;
+constexpr int kMoveThreads = 1024;
 
 // key[perm[q]] = bucket of q: for every packed value of A, the bucket of its
 // position in A^T.
-__global__ void k_bucket_keys(int64_t nnz, const int32_t *__restrict__ perm,
+__global__ void k_bucket_keys(int64_t nnz, int64_t w, const int32_t *__restrict__ perm,
                               int32_t *__restrict__ key) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < nnz) key[perm[q]] = (int32_t)(q / kPermBucket);
+    if (q < nnz) key[perm[q]] = (int32_t)(q / w);
 }
 
 // slot[order[t]] = t: the staging slot of each value of A.
@@ -101,56 +105,112 @@ __global__ void k_invert(int64_t nnz, const int32_t *__restrict__ order,
     if (t < nnz) slot[order[t]] = (int32_t)t;
 }
 
-// perm[q] <- slot[perm[q]] (in place): the staging slot holding A^T's value q.
-__global__ void k_compose(int64_t nnz, const int32_t *__restrict__ slot,
-                          int32_t *__restrict__ perm) {
+// src[q] = slot of A^T's value q, relative to its bucket's first slot.
+__global__ void k_bucket_src(int64_t nnz, int64_t w, const int32_t *__restrict__ slot,
+                             const int32_t *__restrict__ perm, uint16_t *__restrict__ src) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < nnz) perm[q] = slot[perm[q]];
+    if (q < nnz) src[q] = (uint16_t)(slot[perm[q]] - (q / w) * w);
 }
 
-// Pass 1: stage[slot[i]] = in[i].  Each workgroup moves a contiguous chunk of
-// kMoveChunk values of A, so its writes into one bucket's slots form one
-// contiguous run (about kMoveChunk / number of buckets values) that a single
-// L2 assembles into whole lines.
-constexpr int64_t kMoveChunk = 16384;
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_stage_scatter(int64_t n, const int32_t *__restrict__ slot,
-                                                       const T *__restrict__ in,
-                                                       T *__restrict__ stage) {
-    const int64_t i0 = (int64_t)blockIdx.x * kMoveChunk;
-    const int64_t i1 = min(i0 + kMoveChunk, n);
-#pragma unroll 8
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) stage[slot[i]] = in[i];
+// ckey[t] = chunk of A holding the value in slot t.
+__global__ void k_chunk_keys(int64_t nnz, int64_t w, const int32_t *__restrict__ order,
+                             int32_t *__restrict__ ckey) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nnz) ckey[t] = (int32_t)(order[t] / w);
 }
 
-// Pass 2: out[q] = stage[src[q]], src[q] inside q's bucket.  Workgroups reach
-// the kXcds XCDs round robin; XCD x gathers buckets x, x + kXcds, ... and its
-// kGatherPerXcd workgroups split each bucket, so an XCD's L2 holds one
-// bucket's window at a time.
-constexpr int kGatherPerXcd = 128;
+// Pass 1 tables: position j of chunk c's slot-ordered list writes slot
+// by_chunk[j], reading the chunk's local value order[by_chunk[j]] - c*w.
+__global__ void k_chunk_lists(int64_t nnz, int64_t w, const int32_t *__restrict__ order,
+                              const int32_t *__restrict__ by_chunk, uint16_t *__restrict__ lidx) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nnz) lidx[j] = (uint16_t)(order[by_chunk[j]] - (j / w) * w);
+}
 
+// Pass 1: workgroup c loads values [c*W, c*W + m) of A into LDS, then writes
+// stage[gpos[j]] = win[lidx[j]] over its slot-ordered list.  Each thread
+// takes pairs of neighbouring entries, so the index tables load as one 64-bit
+// (gpos) and one 32-bit (lidx) word per pair; a pair at the end of the
+// tables reads into their 64 bytes of trailing padding, and its second entry
+// is dropped.
 template <typename T>
-__global__ __launch_bounds__(256) void k_stage_gather(int64_t n, const int32_t *__restrict__ src,
-                                                      const T *__restrict__ stage,
-                                                      T *__restrict__ out) {
-    constexpr int64_t share = kPermBucket / kGatherPerXcd;
-    const int x = (int)(blockIdx.x % kXcds), j = (int)(blockIdx.x / kXcds);
-    const int64_t nb = (n + kPermBucket - 1) / kPermBucket;
-    for (int64_t b = x; b < nb; b += kXcds) {
-        const int64_t q0 = b * kPermBucket + j * share;
-        const int64_t q1 = min(q0 + share, n);
-        for (int64_t q = q0 + threadIdx.x; q < q1; q += 256) out[q] = stage[src[q]];
+__global__ __launch_bounds__(kMoveThreads) void k_move_chunks(int64_t n,
+                                                              const uint16_t *__restrict__ lidx,
+                                                              const int32_t *__restrict__ gpos,
+                                                              const T *__restrict__ in,
+                                                              T *__restrict__ stage) {
+    constexpr int W = kMoveValues;
+    constexpr int P = W / (2 * kMoveThreads);
+    __shared__ T win[W];
+    const int64_t c0 = (int64_t)blockIdx.x * W;
+    const int m = (int)min((int64_t)W, n - c0);
+    const int th = threadIdx.x;
+    uint64_t g[P];
+    uint32_t l[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+        const int k = 2 * (th + e * kMoveThreads);
+        g[e] = k < m ? *(const uint64_t *)(gpos + c0 + k) : 0;
+        l[e] = k < m ? *(const uint32_t *)(lidx + c0 + k) : 0;
+    }
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+        const int k = 2 * (th + e * kMoveThreads);
+        if (k < m) win[k] = in[c0 + k];
+        if (k + 1 < m) win[k + 1] = in[c0 + k + 1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+        const int k = 2 * (th + e * kMoveThreads);
+        if (k < m) stage[(uint32_t)g[e]] = win[l[e] & 0xffffu];
+        if (k + 1 < m) stage[(uint32_t)(g[e] >> 32)] = win[l[e] >> 16];
+    }
+}
+
+// Pass 2: workgroup b loads bucket b's slots [b*W, b*W + m) into LDS, then
+// writes out[b*W + q] = win[src[b*W + q]]; pairs as in pass 1.
+template <typename T>
+__global__ __launch_bounds__(kMoveThreads) void k_move_buckets(int64_t n,
+                                                               const uint16_t *__restrict__ src,
+                                                               const T *__restrict__ stage,
+                                                               T *__restrict__ out) {
+    constexpr int W = kMoveValues;
+    constexpr int P = W / (2 * kMoveThreads);
+    __shared__ T win[W];
+    const int64_t q0 = (int64_t)blockIdx.x * W;
+    const int m = (int)min((int64_t)W, n - q0);
+    const int th = threadIdx.x;
+    uint32_t l[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+        const int k = 2 * (th + e * kMoveThreads);
+        l[e] = k < m ? *(const uint32_t *)(src + q0 + k) : 0;
+    }
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+        const int k = 2 * (th + e * kMoveThreads);
+        if (k < m) win[k] = stage[q0 + k];
+        if (k + 1 < m) win[k + 1] = stage[q0 + k + 1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+        const int k = 2 * (th + e * kMoveThreads);
+        if (k < m) out[q0 + k] = win[l[e] & 0xffffu];
+        if (k + 1 < m) out[q0 + k + 1] = win[l[e] >> 16];
     }
 }
 
 template <typename T>
 static void launch_move(const spc5_matrix *A, const T *vals, hipStream_t s) {
+    constexpr int64_t W = kMoveValues;
     const int64_t n = A->nnz;
-    hipLaunchKernelGGL(k_stage_scatter<T>, dim3((unsigned)((n + kMoveChunk - 1) / kMoveChunk)),
-                       dim3(256), 0, s, n, A->tr_scatter, vals, (T *)A->tr_stage);
-    hipLaunchKernelGGL(k_stage_gather<T>, dim3(kXcds * kGatherPerXcd), dim3(256), 0, s, n,
-                       A->tr_gather, (const T *)A->tr_stage, (T *)A->tr_vals);
+    const unsigned grid = (unsigned)((n + W - 1) / W);
+    hipLaunchKernelGGL(k_move_chunks<T>, dim3(grid), dim3(kMoveThreads), 0, s, n, A->tr_lidx,
+                       A->tr_gpos, vals, (T *)A->tr_stage);
+    hipLaunchKernelGGL(k_move_buckets<T>, dim3(grid), dim3(kMoveThreads), 0, s, n, A->tr_src,
+                       (const T *)A->tr_stage, (T *)A->tr_vals);
 }
 
 int build_transpose_plan(spc5_matrix *A, int r, int c) {
@@ -163,7 +223,8 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     int64_t *rowptr_t = nullptr;
     void *val_t = nullptr, *tmp = nullptr;
     spc5_matrix *T = nullptr;
-    int32_t *perm = nullptr, *scat = nullptr;
+    int32_t *perm = nullptr;
+    uint16_t *lidx = nullptr, *src = nullptr;
     void *gbuf = nullptr, *stage = nullptr;
     size_t tmp_bytes = 0;
     auto cleanup = [&]() {
@@ -174,7 +235,7 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     auto fail_all = [&](int st) {
         cleanup();
         free_matrix(T);
-        for (void *p : {(void *)perm, (void *)scat, gbuf, stage})
+        for (void *p : {(void *)perm, (void *)lidx, (void *)src, gbuf, stage})
             if (p) (void)hipFree(p);
         return st;
     };
@@ -245,41 +306,55 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     int st = convert_on_device(T, rowptr_t, colidx_t, val_t, idx_s, perm);
     if (st != SPC5_OK) return fail_all(st);
     if ((st = finish_matrix(T)) != SPC5_OK) return fail_all(st);
-    // 4. staging slots: a stable sort of A's packed indices by the bucket of
-    // their A^T position (row_of, col_of and key_s are free again)
-    if ((e = hipMalloc((void **)&scat, nz * 4)) != hipSuccess ||
+    // 4. the value move's tables (row_of, col_of, key_s, idx_s and colidx_t
+    // are free again).  Slots: a stable sort of A's packed indices by the
+    // bucket of their A^T position; pass 1's lists: a stable sort of the
+    // slots by the chunk of A they read.
+    if ((e = hipMalloc((void **)&lidx, nz * 2 + kPad)) != hipSuccess ||
+        (e = hipMalloc((void **)&src, nz * 2 + kPad)) != hipSuccess ||
         (e = hipMalloc(&stage, nz * vb + kPad)) != hipSuccess)
         return fail_all(hip_fail(e, "allocating the transpose plan"));
     if (nnz > 0) {
+        const int64_t w = kMoveValues;
         const unsigned grid = (unsigned)((nnz + 255) / 256);
-        hipLaunchKernelGGL(k_bucket_keys, dim3(grid), dim3(256), 0, s, nnz, perm, row_of);
-        const int64_t nb = (nnz + kPermBucket - 1) / kPermBucket;
+        const int64_t nb = (nnz + w - 1) / w;
         unsigned bits = 1;
         while (bits < 31 && ((int64_t)1 << bits) < nb) ++bits;
-        size_t need = 0;
         rocprim::counting_iterator<int32_t> iota(0);
-        if ((e = rocprim::radix_sort_pairs(nullptr, need, row_of, col_of, iota, key_s,
-                                           (size_t)nnz, 0u, bits, s)) != hipSuccess)
+        auto sort = [&](int32_t *keys, int32_t *keys_out, int32_t *vals_out) -> hipError_t {
+            size_t need = 0;
+            hipError_t e2 = rocprim::radix_sort_pairs(nullptr, need, keys, keys_out, iota,
+                                                      vals_out, (size_t)nnz, 0u, bits, s);
+            if (e2 != hipSuccess) return e2;
+            if (need > tmp_bytes) {
+                if (tmp) (void)hipFree(tmp);
+                tmp = nullptr;
+                if ((e2 = hipMalloc(&tmp, need)) != hipSuccess) return e2;
+                tmp_bytes = need;
+            }
+            return rocprim::radix_sort_pairs(tmp, need, keys, keys_out, iota, vals_out,
+                                             (size_t)nnz, 0u, bits, s);
+        };
+        // order[t] (key_s): the value of A in slot t; slot (col_of) its inverse
+        hipLaunchKernelGGL(k_bucket_keys, dim3(grid), dim3(256), 0, s, nnz, w, perm, row_of);
+        if ((e = sort(row_of, col_of, key_s)) != hipSuccess)
             return fail_all(hip_fail(e, "sorting by bucket"));
-        if (need > tmp_bytes) {
-            if (tmp) (void)hipFree(tmp);
-            tmp = nullptr;
-            if ((e = hipMalloc(&tmp, need)) != hipSuccess)
-                return fail_all(hip_fail(e, "allocating the transpose plan"));
-            tmp_bytes = need;
-        }
-        if ((e = rocprim::radix_sort_pairs(tmp, need, row_of, col_of, iota, key_s, (size_t)nnz,
-                                           0u, bits, s)) != hipSuccess)
-            return fail_all(hip_fail(e, "sorting by bucket"));
-        hipLaunchKernelGGL(k_invert, dim3(grid), dim3(256), 0, s, nnz, key_s, scat);
-        hipLaunchKernelGGL(k_compose, dim3(grid), dim3(256), 0, s, nnz, scat, perm);
+        hipLaunchKernelGGL(k_invert, dim3(grid), dim3(256), 0, s, nnz, key_s, col_of);
+        hipLaunchKernelGGL(k_bucket_src, dim3(grid), dim3(256), 0, s, nnz, w, col_of, perm, src);
+        // pass 1 lists: slots sorted by chunk (stable, so ascending inside a
+        // chunk); gpos (perm's memory) = the slots, lidx = local value index
+        hipLaunchKernelGGL(k_chunk_keys, dim3(grid), dim3(256), 0, s, nnz, w, key_s, row_of);
+        if ((e = sort(row_of, idx_s, perm)) != hipSuccess)
+            return fail_all(hip_fail(e, "sorting by chunk"));
+        hipLaunchKernelGGL(k_chunk_lists, dim3(grid), dim3(256), 0, s, nnz, w, key_s, perm, lidx);
         if ((e = hipGetLastError()) != hipSuccess)
-            return fail_all(hip_fail(e, "building the staging slots"));
+            return fail_all(hip_fail(e, "building the value move"));
     }
     cleanup();
     A->tr = T;
-    A->tr_scatter = scat;
-    A->tr_gather = perm;
+    A->tr_lidx = lidx;
+    A->tr_gpos = perm;
+    A->tr_src = src;
     A->tr_stage = stage;
     A->tr_vals = gbuf;
     return SPC5_OK;

@@ -383,6 +383,52 @@ def test_transpose_plan(A, rc, trc, dev):
     assert np.array_equal(M.transpose(wd).cpu().numpy().view(np.uint64), xb.view(np.uint64))
 
 
+def exact_nnz_matrix(nnz, seed):
+    """Square matrix with exactly `nnz` nonzeros: rows of 16 distinct random
+    columns, the last row shorter; small integer values."""
+    rng = np.random.default_rng(seed)
+    d = 16
+    nrows = (nnz + d - 1) // d
+    ncols = max(nrows, d)
+    counts = np.full(nrows, d, dtype=np.int64)
+    counts[-1] = nnz - d * (nrows - 1)
+    cols = [np.sort(rng.choice(ncols, size=k, replace=False)) for k in counts]
+    colidx = np.concatenate(cols).astype(np.int32)
+    rowptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    values = rng.integers(-3, 4, nnz).astype(np.float64)
+    return rowptr, colidx, values, ncols
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("windows", [0.3, 1.0, 2.0, 2.37])
+@pytest.mark.parametrize("trc", [(1, 8), (4, 4)], ids=lambda t: "b%d_%d" % t)
+def test_transpose_plan_value_move(dtype, windows, trc, dev):
+    """Caller values theta reach A^T's order in two passes through LDS windows
+    of 16384 values: nnz below one window, exactly one and two windows, and a
+    ragged multi-window tail.  Integer data, so the product is exact and
+    compared bit for bit with the oracle."""
+    S = spc5()
+    w = 16384
+    nnz = int(round(windows * w))
+    rowptr, colidx, values, ncols = exact_nnz_matrix(nnz, seed=61)
+    say(f"transpose value move {dtype} nnz={nnz} A^T beta{trc}")
+    M = S.Spc5Matrix.from_csr(rowptr, colidx, values, ncols, 1, 8, dtype)
+    assert M.info.nnz == nnz
+    M.prepare_transpose(*trc)
+    rng = np.random.default_rng(62)
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    wv = rng.integers(-4, 5, len(rowptr) - 1).astype(np.float64)
+    theta = rng.integers(-3, 4, nnz).astype(np.float64)   # beta(1,8): packed order = CSR order
+    xt = M.transpose(to_dev(wv, dev, tdt), values=to_dev(theta, dev, tdt)).cpu().double().numpy()
+    ref = oracle.csr_spmv_t(rowptr, colidx, theta, wv, ncols)
+    assert np.array_equal(xt, ref)
+    # the matrix's own values, then theta equal to them: the same bits
+    xo = M.transpose(to_dev(wv, dev, tdt)).cpu().double().numpy()
+    assert np.array_equal(xo, oracle.csr_spmv_t(rowptr, colidx, values, wv, ncols))
+    xs = M.transpose(to_dev(wv, dev, tdt), values=to_dev(values, dev, tdt)).cpu().double().numpy()
+    assert np.array_equal(xs, xo)
+
+
 @pytest.mark.parametrize("plan", [False, True], ids=["scatter", "plan"])
 @pytest.mark.parametrize("rc", MAIN + [(8, 8), (3, 5)], ids=lambda t: "b%d_%d" % t)
 def test_transpose_unit_rows_and_integers(rc, plan, dev):
