@@ -162,6 +162,43 @@ def test_spmv_deterministic(rc, kernel, dev):
         assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
 
 
+@pytest.mark.parametrize("kernel", ["auto", "staged", "sweep", "rows"])
+@pytest.mark.parametrize("rc", [(1, 8), (1, 16), (2, 4), (4, 4), (8, 8), (3, 5), (4, 8)],
+                         ids=lambda t: "b%d_%d" % t)
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_nonfinite_x_stays_in_its_rows(rc, kernel, dtype, dev):
+    """x holds NaN and Inf in some columns.  The kernels read whole x windows
+    of c columns per block (the union of the block's rows), so a non-finite
+    entry of a column that another row of the block uses, or that no row
+    uses, lies inside rows' windows: it must not reach those rows.  The NaN /
+    Inf pattern of y must be the oracle's, and the finite rows must match."""
+    r, c = rc
+    A = W.random_sparse(300, 257, 0.03, seed=71)
+    rng = np.random.default_rng(72)
+    x = A.x.copy()
+    bad = rng.choice(A.ncols, size=26, replace=False)
+    x[bad[:13]] = np.nan
+    x[bad[13:]] = np.inf
+    say(f"non-finite x beta{rc} {kernel} {dtype}")
+    S = spc5()
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c, dtype)
+    if kernel != "auto":
+        M.set_schedule(kernel)
+        assert M.kernel == kernel
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    y = M.spmv(to_dev(x, dev, tdt)).cpu().double().numpy()
+    v, xr = (A.values, x) if dtype == "float64" else (
+        A.values.astype(np.float32).astype(np.float64), x.astype(np.float32).astype(np.float64))
+    with np.errstate(invalid="ignore"):
+        ref = oracle.csr_spmv(A.rowptr, A.colidx, v, xr)
+    assert np.isnan(ref).any() and np.isinf(ref).any() and np.isfinite(ref).any()
+    assert np.array_equal(np.isnan(y), np.isnan(ref))
+    assert np.array_equal(np.isposinf(y), np.isposinf(ref))
+    assert np.array_equal(np.isneginf(y), np.isneginf(ref))
+    fin = np.isfinite(ref)
+    assert oracle.rel_l2(y[fin], ref[fin]) <= (1e-14 if dtype == "float64" else 1e-6)
+
+
 def test_spmv_overwrites_y(dev):
     A = W.random_sparse(50, 40, 0.05, seed=15)    # has empty rows
     S = spc5()
