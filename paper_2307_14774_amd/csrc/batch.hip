@@ -119,9 +119,10 @@ struct BatchFix {
     int32_t mat, row, t0, t1;
 };
 
-// 16-byte value vectors per thread of a value-mode tile: kValueTile values,
+// 16-byte value vectors per thread of a value-mode tile: value_tile() values,
 // the cap of the batch-private schedules.
-template <typename T> constexpr int kBatchNVG = kValueTile * (int)sizeof(T) / 4096;
+template <typename T>
+constexpr int kBatchNVG = value_tile((int)sizeof(T)) * (int)sizeof(T) / 4096;
 
 // Shared memory of one value-mode tile (sized for the widest mask type).
 template <typename T>
@@ -598,7 +599,7 @@ int spc5_batch_create(int nmat, spc5_matrix *const *mats, spc5_batch **out) {
                 return st;
             }
             const int sz = A->dtype == SPC5_F64 ? 8 : 4;
-            if ((int64_t)S.max_tile_values * sz + 16 > (int64_t)kValueTile * sz) {
+            if ((int64_t)S.max_tile_values * sz + 16 > (int64_t)value_tile(sz) * sz) {
                 spc5_batch_free(B);
                 return fail(SPC5_EUNSUPPORTED, "batch tile exceeds its LDS value buffer");
             }

@@ -34,9 +34,11 @@ struct StreamCfg {
     static constexpr int U = R * C <= 16 ? 4 : 2;                      // blocks per step
 };
 
-// Values per value-mode (beta(1,c)) tile, 16 bytes of padding included: 8 KiB
-// of LDS in FP32, 16 KiB in FP64.
-constexpr int kValueTile = 2048;
+// Values per value-mode (beta(1,c)) tile for an element of sz bytes, 16 bytes
+// of padding included: 8 KiB of LDS in FP32, 12 KiB in FP64.  Each value also
+// keeps its decoded column in LDS; these sizes leave room for 5-6 resident
+// workgroups per compute unit, which the per-nonzero gathers need.
+constexpr int value_tile(int sz) { return sz == 8 ? 1536 : 2048; }
 
 // Tile capacities for a matrix (must match StreamCfg).
 void staged_caps(const spc5_matrix *A, int *vt, int *bt, int *ppw);

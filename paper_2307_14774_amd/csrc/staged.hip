@@ -42,10 +42,7 @@ namespace spc5 {
 void staged_caps(const spc5_matrix *A, int *vt, int *bt, int *ppw) {
     const int sz = A->dtype == SPC5_F64 ? 8 : 4;
     const int cm = A->c <= 4 ? 4 : (A->c <= 8 ? 8 : 16);
-    // value mode keeps a second LDS array per value (its decoded column):
-    // about kValueTile values per tile keep enough workgroups per compute
-    // unit for the latency-bound per-nonzero gathers
-    *vt = ((A->r == 1 ? kValueTile * sz : 16384) - 16) / sz;
+    *vt = ((A->r == 1 ? value_tile(sz) * sz : 16384) - 16) / sz;
     *bt = A->r == 1 ? 4 * kWG : std::min(256, 8192 / (cm * sz));
     *ppw = kWG / A->r;
 }
@@ -707,21 +704,19 @@ static bool sparse_rows(const spc5_matrix *A) {
     return A->nblocks > 0 && 2.0 * (double)A->nnz < (double)A->nblocks * A->r * A->c;
 }
 
-// LDS value buffer sized to the largest tile of the matrix: 4, 8, 12 (r > 1)
-// or 16 KiB (value-mode tiles at most kValueTile values).
+// LDS value buffer sized to the largest tile of the matrix: 4, 8, 12 or 16
+// KiB (value-mode tiles at most value_tile() values).
 template <typename T, int R, int C, bool SPARSE>
 static hipError_t launch_stream_s(const spc5_matrix *A, const T *val, const T *x, T *y,
                                   hipStream_t s, int remap) {
     const int64_t need = (int64_t)A->max_tile_values * (int64_t)sizeof(T) + 16;
     if (need <= 4096) return launch_stream_g<T, R, C, 1, SPARSE>(A, val, x, y, s, remap);
     if (need <= 8192) return launch_stream_g<T, R, C, 2, SPARSE>(A, val, x, y, s, remap);
-    if constexpr (R > 1) {
-        // a 12 KiB buffer where the tiles fit: one more resident workgroup per
-        // compute unit (FP64 beta(4,4) Laplacian: 6 instead of 5)
-        if (need <= 12288) return launch_stream_g<T, R, C, 3, SPARSE>(A, val, x, y, s, remap);
-    }
-    // value-mode tiles stop at kValueTile values: 8 KiB in FP32
-    if constexpr (R == 1 && sizeof(T) == 4) return hipErrorInvalidValue;
+    // a 12 KiB buffer where the tiles fit: one more resident workgroup per
+    // compute unit (FP64 beta(4,4) Laplacian: 6 instead of 5)
+    if (need <= 12288) return launch_stream_g<T, R, C, 3, SPARSE>(A, val, x, y, s, remap);
+    // value-mode tiles stop at value_tile() values (8 or 12 KiB)
+    if constexpr (R == 1) return hipErrorInvalidValue;
     else return launch_stream_g<T, R, C, 4, SPARSE>(A, val, x, y, s, remap);
 }
 
