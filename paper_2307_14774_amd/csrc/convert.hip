@@ -5,7 +5,9 @@
 // smallest column not yet covered among the panel's rows and takes, in every
 // row, the nonzeros of columns [anchor, anchor+c).  Each panel is blocked
 // independently by one thread (two passes: count, then fill after an
-// exclusive scan of the per-panel counts gives every panel its first block).
+// exclusive scan of the per-panel counts gives every panel its first block);
+// for r = 1 a row longer than kLongRow nonzeros is blocked by a whole
+// wavefront instead (k_block_long_rows), with the same greedy rule.
 // A panel's packed values occupy exactly the CSR value range of its rows, so
 // the fill pass writes them at rowptr[first row of the panel] onward without
 // any further scan.
@@ -18,6 +20,7 @@
 namespace spc5 {
 
 constexpr int kMaxR = 8;
+constexpr int64_t kLongRow = 2048;
 
 template <bool FILL, typename T, typename MT>
 __global__ __launch_bounds__(256) void k_block_panels(
@@ -28,6 +31,7 @@ __global__ __launch_bounds__(256) void k_block_panels(
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npanels) return;
+    if (r == 1 && rowptr[p + 1] - rowptr[p] > kLongRow) return;    // k_block_long_rows
     const int64_t row0 = p * r;
     const int nr = (int)min((int64_t)r, nrows - row0);
     const int64_t kNone = INT64_MAX;
@@ -62,6 +66,80 @@ __global__ __launch_bounds__(256) void k_block_panels(
         ++nb;
     }
     if (!FILL) count[p] = nb;
+}
+
+// beta(1,c) rows longer than kLongRow nonzeros, one wavefront each.  The
+// lanes hold 64 consecutive columns at a time; the columns below the open
+// block's end join it (their bits OR-reduced into its mask), and the first
+// column at or past the end opens the next block -- the greedy rule of the
+// thread walk, so the blocks are the same.  With r = 1 the packed values are
+// the row's CSR values in order.
+template <bool FILL, typename T, typename MT>
+__global__ __launch_bounds__(256) void k_block_long_rows(
+    int64_t nrows, int c, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    const T *__restrict__ vin, int64_t *__restrict__ count, const int64_t *__restrict__ bptr,
+    int32_t *__restrict__ bcol, MT *__restrict__ masks, T *__restrict__ vout)
+{
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (row >= nrows) return;
+    const int64_t b = rowptr[row], e = rowptr[row + 1];
+    if (e - b <= kLongRow) return;    // uniform over the wavefront
+    const int lane = lane_id();
+    const int64_t first = FILL ? bptr[row] : 0;
+    int64_t nb = 0, anchor = 0, lim = INT64_MIN;
+    unsigned m = 0;
+    bool open = false;
+    for (int64_t base = b; base < e; base += kWave) {
+        const int64_t k = base + lane;
+        const bool valid = k < e;
+        const int64_t x = valid ? (int64_t)colidx[k] : INT64_MAX;
+        if (FILL && valid) vout[k] = vin[k];
+        uint64_t pend = __ballot(valid);
+        while (pend) {
+            const uint64_t cov = __ballot(valid && x < lim) & pend;
+            unsigned bit = ((cov >> lane) & 1ull) ? 1u << (unsigned)(x - anchor) : 0u;
+            for (int d = 1; d < kWave; d <<= 1) bit |= __shfl_xor(bit, d);
+            m |= bit;
+            pend &= ~cov;
+            if (pend) {
+                if (open) {
+                    if (FILL && lane == 0) {
+                        bcol[first + nb] = (int32_t)anchor;
+                        masks[first + nb] = (MT)m;
+                    }
+                    ++nb;
+                }
+                anchor = __shfl(x, __ffsll((unsigned long long)pend) - 1);
+                lim = anchor + c;
+                m = 0;
+                open = true;
+            }
+        }
+    }
+    if (open) {
+        if (FILL && lane == 0) {
+            bcol[first + nb] = (int32_t)anchor;
+            masks[first + nb] = (MT)m;
+        }
+        ++nb;
+    }
+    if (!FILL && lane == 0) count[row] = nb;
+}
+
+// Both walks over all panels (the long-row one only for r = 1).
+template <bool FILL, typename T, typename MT>
+static void launch_walk(const spc5_matrix *A, const int64_t *rowptr, const int32_t *colidx,
+                        const T *vin, int64_t *count, const int64_t *bptr, int32_t *bcol,
+                        MT *masks, T *vout, hipStream_t s) {
+    const int64_t grid = (A->npanels + 255) / 256;
+    if (grid == 0) return;
+    hipLaunchKernelGGL((k_block_panels<FILL, T, MT>), dim3((unsigned)grid), dim3(256), 0, s,
+                       A->nrows, A->npanels, A->r, A->c, rowptr, colidx, vin, count, bptr, bcol,
+                       masks, vout);
+    if (A->r == 1)
+        hipLaunchKernelGGL((k_block_long_rows<FILL, T, MT>),
+                           dim3((unsigned)((A->nrows * kWave + 255) / 256)), dim3(256), 0, s,
+                           A->nrows, A->c, rowptr, colidx, vin, count, bptr, bcol, masks, vout);
 }
 
 // ---- exclusive scan of int64 counts: out[0..n] with out[n] = total ----------
@@ -180,17 +258,12 @@ template <typename T, typename MT>
 static hipError_t launch_block(bool fill, spc5_matrix *A, const int64_t *rowptr,
                                const int32_t *colidx, const void *vin, int64_t *count,
                                const int64_t *bptr, hipStream_t s) {
-    const int64_t grid = (A->npanels + 255) / 256;
-    if (grid == 0) return hipSuccess;
     if (fill)
-        hipLaunchKernelGGL((k_block_panels<true, T, MT>), dim3((unsigned)grid), dim3(256), 0, s,
-                           A->nrows, A->npanels, A->r, A->c, rowptr, colidx, (const T *)vin,
-                           count, bptr, A->blk_col, (MT *)A->masks, (T *)A->val);
+        launch_walk<true, T, MT>(A, rowptr, colidx, (const T *)vin, count, bptr, A->blk_col,
+                                 (MT *)A->masks, (T *)A->val, s);
     else
-        hipLaunchKernelGGL((k_block_panels<false, T, MT>), dim3((unsigned)grid), dim3(256), 0,
-                           s, A->nrows, A->npanels, A->r, A->c, rowptr, colidx,
-                           (const T *)vin, count, bptr, (int32_t *)nullptr, (MT *)nullptr,
-                           (T *)nullptr);
+        launch_walk<false, T, MT>(A, rowptr, colidx, (const T *)vin, count, bptr, nullptr,
+                                  nullptr, nullptr, s);
     return hipGetLastError();
 }
 
@@ -301,17 +374,13 @@ int convert_on_device(spc5_matrix *A, const int64_t *d_rowptr, const int32_t *d_
     if (d_payload && d_payload_out && A->npanels > 0) {
         // the same walk once more with an int32 payload in place of the
         // values (anchors and masks are rewritten with identical contents)
-        const unsigned grid = (unsigned)((A->npanels + 255) / 256);
         if (A->mask_bytes == 1)
-            hipLaunchKernelGGL((k_block_panels<true, int32_t, uint8_t>), dim3(grid), dim3(256), 0,
-                               s, A->nrows, A->npanels, A->r, A->c, d_rowptr, d_colidx,
-                               d_payload, (int64_t *)nullptr, bptr64, A->blk_col,
-                               (uint8_t *)A->masks, d_payload_out);
+            launch_walk<true, int32_t, uint8_t>(A, d_rowptr, d_colidx, d_payload, nullptr, bptr64,
+                                                A->blk_col, (uint8_t *)A->masks, d_payload_out, s);
         else
-            hipLaunchKernelGGL((k_block_panels<true, int32_t, uint16_t>), dim3(grid), dim3(256),
-                               0, s, A->nrows, A->npanels, A->r, A->c, d_rowptr, d_colidx,
-                               d_payload, (int64_t *)nullptr, bptr64, A->blk_col,
-                               (uint16_t *)A->masks, d_payload_out);
+            launch_walk<true, int32_t, uint16_t>(A, d_rowptr, d_colidx, d_payload, nullptr,
+                                                 bptr64, A->blk_col, (uint16_t *)A->masks,
+                                                 d_payload_out, s);
         if ((e = hipGetLastError()) != hipSuccess) {
             cleanup();
             return hip_fail(e, "placing the payload");

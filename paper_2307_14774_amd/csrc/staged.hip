@@ -442,7 +442,7 @@ __global__ __launch_bounds__(kWG) void k_spmv_vstream(
 // panels of each group, pass 1 writes them.
 template <typename MT>
 __global__ void k_tile_groups(int pass, int64_t npanels, int r, int ppw, int vt, int bt,
-                              const int32_t *bp, const int32_t *pv, const MT *masks,
+                              const int32_t *bp, const int32_t *pv, const int64_t *vpre,
                               int64_t *count, const int64_t *first, int64_t *scount,
                               const int64_t *sfirst, int32_t *tp, int32_t *tb, int32_t *tv,
                               int32_t *tf, int32_t *sp, int32_t *st0, int32_t *st1,
@@ -471,20 +471,26 @@ __global__ void k_tile_groups(int pass, int64_t npanels, int r, int ppw, int vt,
                 sp[so + ns] = (int32_t)p;
                 st0[so + ns] = (int32_t)(o + n);
             }
-            int v = pv[p], pb = bp[p], pvv = pv[p];
-            emit(p, pb, pvv, 1);
-            for (int b = bp[p]; b < bp[p + 1]; ++b) {
-                int cnt = 0;
-                for (int i = 0; i < r; ++i) cnt += __popc((unsigned)masks[(int64_t)b * r + i]);
-                if (b + 1 - pb > bt || v + cnt - pvv > vt) {
-                    atomicMax(maxvals, v - pvv);
-                    pb = b;
-                    pvv = v;
-                    emit(p, pb, pvv, 1);
+            // pieces: from block pb, the longest run [pb, e) with at most bt
+            // blocks and vt values (vpre: values before each block), found by
+            // binary search -- the same cuts as a walk over the blocks
+            const int be = bp[p + 1];
+            int pb = bp[p];
+            int64_t pvv = pv[p];
+            emit(p, pb, (int)pvv, 1);
+            for (;;) {
+                int lo = pb + 1, hi = min(pb + bt, be);   // one block never exceeds vt
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) / 2;
+                    if (vpre[mid] - pvv <= vt) lo = mid;
+                    else hi = mid - 1;
                 }
-                v += cnt;
+                atomicMax(maxvals, (int)(vpre[lo] - pvv));
+                if (lo >= be) break;
+                pb = lo;
+                pvv = vpre[lo];
+                emit(p, pb, (int)pvv, 1);
             }
-            atomicMax(maxvals, v - pvv);
             if (pass) st1[so + ns] = (int32_t)(o + n - 1);
             ++ns;
             continue;
@@ -536,13 +542,30 @@ __global__ __launch_bounds__(256) void k_split_fixup(int64_t nsplit, int r, int6
 
 template <typename MT>
 static void launch_tile_groups(unsigned grid, int pass, const spc5_matrix *A, int ppw, int vt,
-                               int bt, int64_t *count, const int64_t *first, int64_t *scount,
-                               const int64_t *sfirst, int32_t *tp, int32_t *tb, int32_t *tv,
-                               int32_t *tf, int32_t *sp, int32_t *st0, int32_t *st1,
+                               int bt, const int64_t *vpre, int64_t *count, const int64_t *first,
+                               int64_t *scount, const int64_t *sfirst, int32_t *tp, int32_t *tb,
+                               int32_t *tv, int32_t *tf, int32_t *sp, int32_t *st0, int32_t *st1,
                                int *maxvals) {
     hipLaunchKernelGGL(k_tile_groups<MT>, dim3(grid), dim3(256), 0, nullptr, pass, A->npanels,
-                       A->r, ppw, vt, bt, A->blk_ptr, A->panel_val, (const MT *)A->masks,
-                       count, first, scount, sfirst, tp, tb, tv, tf, sp, st0, st1, maxvals);
+                       A->r, ppw, vt, bt, A->blk_ptr, A->panel_val, vpre, count, first, scount,
+                       sfirst, tp, tb, tv, tf, sp, st0, st1, maxvals);
+}
+
+// flag = 1 when some panel is longer than a tile (vt values or bt blocks).
+__global__ void k_flag_long(int64_t npanels, const int32_t *bp, const int32_t *pv, int vt,
+                            int bt, int *flag) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < npanels && (pv[p + 1] - pv[p] > vt || bp[p + 1] - bp[p] > bt)) *flag = 1;
+}
+
+// Values of every block (popcount of its r row masks).
+template <typename MT>
+__global__ void k_block_values(int64_t nblocks, int r, const MT *masks, int64_t *cnt) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblocks) return;
+    int n = 0;
+    for (int i = 0; i < r; ++i) n += __popc((unsigned)masks[b * r + i]);
+    cnt[b] = n;
 }
 
 void free_staged_schedule(spc5_matrix *A) {
@@ -576,11 +599,13 @@ int build_staged_schedule(spc5_matrix *A, int ppw_req, bool alone) {
     hipStream_t s = nullptr;
     hipError_t e;
     int64_t *count = nullptr, *first = nullptr, *scount = nullptr, *sfirst = nullptr;
-    int64_t *scratch = nullptr, *scratch2 = nullptr;
+    int64_t *scratch = nullptr, *scratch2 = nullptr, *bcnt = nullptr, *vpre = nullptr;
+    int64_t *scratch3 = nullptr;
     int *maxv = nullptr;
     auto cleanup = [&]() {
         for (void *p : {(void *)count, (void *)first, (void *)scount, (void *)sfirst,
-                        (void *)scratch, (void *)scratch2, (void *)maxv})
+                        (void *)scratch, (void *)scratch2, (void *)maxv, (void *)bcnt,
+                        (void *)vpre, (void *)scratch3})
             if (p) (void)hipFree(p);
     };
     auto bail = [&](hipError_t err, const char *what) {
@@ -598,15 +623,40 @@ int build_staged_schedule(spc5_matrix *A, int ppw_req, bool alone) {
         (e = hipMalloc((void **)&sfirst, (size_t)(ng + 1) * 8)) != hipSuccess ||
         (e = hipMalloc((void **)&maxv, 8)) != hipSuccess)
         return bail(e, "allocating the tile schedule");
-    if ((e = zero_fill(maxv, 1, 4, s)) != hipSuccess) return bail(e, "clearing the schedule");
+    if ((e = zero_fill(maxv, 2, 4, s)) != hipSuccess) return bail(e, "clearing the schedule");
+    // panels longer than a tile: values before every block, for the piece cuts
+    hipLaunchKernelGGL(k_flag_long, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, np,
+                       A->blk_ptr, A->panel_val, vt, bt, maxv + 1);
+    int has_long = 0;
+    if ((e = hipGetLastError()) != hipSuccess ||
+        (e = hipMemcpy(&has_long, maxv + 1, 4, hipMemcpyDeviceToHost)) != hipSuccess)
+        return bail(e, "scanning panel lengths");
+    if (has_long) {
+        const int64_t nb = A->nblocks;
+        if ((e = hipMalloc((void **)&bcnt, (size_t)std::max<int64_t>(nb, 1) * 8)) != hipSuccess ||
+            (e = hipMalloc((void **)&vpre, (size_t)(nb + 1) * 8)) != hipSuccess)
+            return bail(e, "allocating the tile schedule");
+        const unsigned gb = (unsigned)((nb + 255) / 256);
+        if (nb > 0) {
+            if (m8)
+                hipLaunchKernelGGL(k_block_values<uint8_t>, dim3(gb), dim3(256), 0, s, nb, A->r,
+                                   (const uint8_t *)A->masks, bcnt);
+            else
+                hipLaunchKernelGGL(k_block_values<uint16_t>, dim3(gb), dim3(256), 0, s, nb,
+                                   A->r, (const uint16_t *)A->masks, bcnt);
+        }
+        if ((e = hipGetLastError()) != hipSuccess ||
+            (e = excl_scan_i64(bcnt, nb, vpre, s, &scratch3)) != hipSuccess)
+            return bail(e, "counting block values");
+    }
     if (m8)
-        launch_tile_groups<uint8_t>(grid, 0, A, ppw, vt, bt, count, nullptr, scount, nullptr,
+        launch_tile_groups<uint8_t>(grid, 0, A, ppw, vt, bt, vpre, count, nullptr, scount,
                                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                    nullptr, maxv);
+                                    nullptr, nullptr, maxv);
     else
-        launch_tile_groups<uint16_t>(grid, 0, A, ppw, vt, bt, count, nullptr, scount, nullptr,
+        launch_tile_groups<uint16_t>(grid, 0, A, ppw, vt, bt, vpre, count, nullptr, scount,
                                      nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                     nullptr, maxv);
+                                     nullptr, nullptr, maxv);
     if ((e = hipGetLastError()) != hipSuccess ||
         (e = excl_scan_i64(count, ng, first, s, &scratch)) != hipSuccess ||
         (e = excl_scan_i64(scount, ng, sfirst, s, &scratch2)) != hipSuccess)
@@ -633,13 +683,13 @@ int build_staged_schedule(spc5_matrix *A, int ppw_req, bool alone) {
          (e = hipMalloc(&A->partial, nt1 * (size_t)A->r * vb)) != hipSuccess))
         return bail(e, "allocating the tile schedule");
     if (m8)
-        launch_tile_groups<uint8_t>(grid, 1, A, ppw, vt, bt, nullptr, first, nullptr, sfirst,
-                                    A->tile_p, A->tile_b, A->tile_v, A->tile_f, A->split_p,
-                                    A->split_t0, A->split_t1, maxv);
+        launch_tile_groups<uint8_t>(grid, 1, A, ppw, vt, bt, vpre, nullptr, first, nullptr,
+                                    sfirst, A->tile_p, A->tile_b, A->tile_v, A->tile_f,
+                                    A->split_p, A->split_t0, A->split_t1, maxv);
     else
-        launch_tile_groups<uint16_t>(grid, 1, A, ppw, vt, bt, nullptr, first, nullptr, sfirst,
-                                     A->tile_p, A->tile_b, A->tile_v, A->tile_f, A->split_p,
-                                     A->split_t0, A->split_t1, maxv);
+        launch_tile_groups<uint16_t>(grid, 1, A, ppw, vt, bt, vpre, nullptr, first, nullptr,
+                                     sfirst, A->tile_p, A->tile_b, A->tile_v, A->tile_f,
+                                     A->split_p, A->split_t0, A->split_t1, maxv);
     hipLaunchKernelGGL(k_tile_sentinel, dim3(1), dim3(1), 0, s, np, ntiles, A->blk_ptr,
                        A->panel_val, A->tile_p, A->tile_b, A->tile_v, A->tile_f);
     int hmax = 0;

@@ -92,6 +92,58 @@ def test_conversion_bit_exact(A, rc, dev):
     assert np.array_equal(va.view(np.uint64), O.values.view(np.uint64))
 
 
+def long_rows_matrix(seed):
+    """Rows at and past the one-thread walk's limit of 2048 nonzeros (2048,
+    2049, 2111, 5000, 9999), with dense, sparse and run-and-gap columns, so
+    that blocks straddle the 64-column chunks of the wavefront walk."""
+    rng = np.random.default_rng(seed)
+    ncols = 40000
+    rows = []
+    for n, kind in [(2048, "sparse"), (2049, "dense"), (2111, "runs"), (5000, "sparse"),
+                    (9999, "runs"), (37, "sparse"), (0, "sparse"), (2500, "dense")]:
+        if kind == "dense":
+            start = int(rng.integers(0, ncols - n))
+            cols = np.arange(start, start + n)
+        elif kind == "sparse":
+            cols = np.sort(rng.choice(ncols, size=n, replace=False))
+        else:
+            runs, total = [], 0
+            pos = int(rng.integers(0, 50))
+            while total < n:
+                ln = int(min(rng.integers(1, 20), n - total))
+                runs.append(np.arange(pos, pos + ln))
+                total += ln
+                pos += ln + int(rng.integers(1, 12))
+            cols = np.concatenate(runs)
+        rows.append(cols)
+    counts = np.array([len(c) for c in rows])
+    rowptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    colidx = np.concatenate(rows).astype(np.int32)
+    values = rng.uniform(-1, 1, colidx.size)
+    x = rng.uniform(-1, 1, ncols)
+    return W.Csr(len(rows), ncols, rowptr, colidx, values, x, "long_rows")
+
+
+@pytest.mark.parametrize("c", [1, 3, 5, 8, 16])
+def test_conversion_long_rows_r1(c, dev):
+    """beta(1,c) rows longer than 2048 nonzeros are blocked by one wavefront
+    each: the same blocks, bit for bit, as the oracle's greedy conversion."""
+    A = long_rows_matrix(81 + c)
+    say(f"long-row conversion beta(1,{c})")
+    S = spc5()
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 1, c)
+    bp, bc, mk, va = M.export()
+    O = oracle.csr_to_spc5(A.rowptr, A.colidx, A.values, A.ncols, 1, c)
+    assert M.info.nblocks == O.nblocks
+    assert np.array_equal(bp, O.blk_ptr)
+    assert np.array_equal(bc, O.blk_col)
+    assert np.array_equal(mk.astype(np.uint16), O.masks)
+    assert np.array_equal(va.view(np.uint64), O.values.view(np.uint64))
+    assert S.plan(A.rowptr, A.colidx, A.ncols, [(1, c)]) == [O.nblocks]
+    y = M.spmv(to_dev(A.x, dev)).cpu().numpy()
+    assert oracle.rel_l2(y, oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)) <= 1e-14
+
+
 # ------------------------------------------------------------ forward
 
 @pytest.mark.parametrize("A", CASES, ids=lambda a: a.name)
