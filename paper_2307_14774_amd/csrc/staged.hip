@@ -180,7 +180,7 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
     const int lane = lane_id();
     const int wv = th / kWave;
     if (th == 0) s_zero[0] = T(0);   // published by the first tile's barrier
-    const int64_t g = remap ? xcd_remap(blockIdx.x, nwg) : (int64_t)blockIdx.x;
+    const int64_t g = remap ? xcd_chunks(blockIdx.x, nwg, kXcdRun) : (int64_t)blockIdx.x;
     const int64_t t_begin = g * tiles_per_wg;
     const int64_t t_end = min(t_begin + tiles_per_wg, ntiles);
     const Buf xbuf = make_buf(x, ncols * (int64_t)sizeof(T));
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(kWG) void k_spmv_vstream(
     const int th = threadIdx.x;
     const int lane = lane_id();
     const int wv = th / kWave;
-    const int64_t g = remap ? xcd_remap(blockIdx.x, nwg) : (int64_t)blockIdx.x;
+    const int64_t g = remap ? xcd_chunks(blockIdx.x, nwg, kXcdRun) : (int64_t)blockIdx.x;
     const int64_t t_begin = g * tiles_per_wg;
     const int64_t t_end = min(t_begin + tiles_per_wg, ntiles);
     const Buf xbuf = make_buf(x, ncols * (int64_t)sizeof(T));

@@ -33,6 +33,18 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n) {
     return xcd * q + (xcd < rem ? xcd : rem) + idx;
 }
 
+// Runs of g consecutive work items per XCD, the runs dealt round robin:
+// neighbouring items still share one XCD's L2, and every XCD gets items from
+// the whole range, so a range whose cost changes along it (a graph transpose:
+// dense hub rows first, scattered tail rows after) stays balanced.  Items past
+// the last full round keep their own index.
+__device__ __forceinline__ int64_t xcd_chunks(int64_t bid, int64_t n, int g) {
+    const int64_t full = (n / (kXcds * (int64_t)g)) * kXcds * g;
+    if (bid >= full) return bid;
+    const int64_t xcd = bid % kXcds, idx = bid / kXcds;
+    return ((idx / g) * kXcds + xcd) * g + idx % g;
+}
+
 // Raw buffer loads.  A load whose byte offset lies at or beyond the
 // descriptor's record count returns 0 and moves no data, which gives
 // predicated gathers without branches: the lanes whose mask bit is clear pass
