@@ -10,6 +10,7 @@
 // their contributions column by column with cross-lane shuffles, so a block
 // issues at most one atomic per column instead of one per nonzero.
 #include "spc5_internal.h"
+#include "stage.h"
 #include "tile.h"
 
 namespace spc5 {
@@ -159,8 +160,119 @@ hipError_t launch_transpose(const spc5_matrix *A, const void *val, const void *y
                                 : tr_dispatch<float>(A, val, ybar, xbar, s);
 }
 
+// Values gradient for beta(1,c) (every block one row) over the staged tile
+// schedule, one workgroup per tile.  The tile's row masks, anchors and panel
+// bounds are read once; a scan of the block popcounts gives every block its
+// first value slot; one thread per BPT consecutive blocks decodes the slots'
+// columns and rows into LDS; then consecutive threads take consecutive slots,
+// vbar[v] = ybar[row(v)] * x[col(v)], so the stores are contiguous and all
+// gathers of a thread are in flight together.
+template <typename T, int C>
+__global__ __launch_bounds__(kWG) void k_values_grad_v(
+    int64_t ntiles, const int32_t *__restrict__ tile_p, const int32_t *__restrict__ tile_b,
+    const int32_t *__restrict__ tile_v, const int32_t *__restrict__ tile_f,
+    const int32_t *__restrict__ blk_ptr, const int32_t *__restrict__ blk_col,
+    const typename MaskOf<C>::type *__restrict__ masks, const T *__restrict__ ybar,
+    const T *__restrict__ x, T *__restrict__ vbar)
+{
+    constexpr int BPT = 4;                                   // blocks per thread
+    constexpr int VMAX = value_tile((int)sizeof(T));         // values per tile
+    constexpr int NX = (VMAX + kWG - 1) / kWG;
+    __shared__ int s_vcol[VMAX];
+    __shared__ int s_vrow[VMAX];
+    __shared__ int s_bp[kWG + 1];
+    __shared__ int s_wsum[kWG / kWave];
+    const int th = threadIdx.x, lane = lane_id(), wv = th / kWave;
+    const int64_t t = xcd_chunks(blockIdx.x, ntiles, kXcdRun);
+    const int f = tile_f[t];
+    const int p0 = tile_p[t], p1 = f ? p0 + 1 : tile_p[t + 1];
+    const int b0 = tile_b[t], nbt = tile_b[t + 1] - b0;
+    const int v0 = tile_v[t], nv = tile_v[t + 1] - v0;
+    const int np = p1 - p0;
+    for (int i = th; i <= np; i += kWG) s_bp[i] = blk_ptr[p0 + i];
+    unsigned m[BPT];
+    int col[BPT];
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const int tb = th * BPT + k;
+        const bool ok = tb < nbt;
+        m[k] = ok ? (unsigned)masks[b0 + tb] : 0u;
+        col[k] = ok ? blk_col[b0 + tb] : 0;
+        cnt += __popc(m[k]);
+    }
+    const int incl = wave_incl_scan(cnt);
+    if (lane == kWave - 1) s_wsum[wv] = incl;
+    __syncthreads();
+    int off = incl - cnt;
+#pragma unroll
+    for (int w2 = 0; w2 < kWG / kWave; ++w2) off += w2 < wv ? s_wsum[w2] : 0;
+    // row of my first block: the last panel starting at or before it
+    int pl = 0;
+    {
+        const int b = b0 + th * BPT;
+        int lo = 0, hi = np - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (s_bp[mid] <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        pl = lo;
+    }
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const int tb = th * BPT + k;
+        if (tb >= nbt) break;
+        while (pl + 1 < np && s_bp[pl + 1] <= b0 + tb) ++pl;
+        unsigned mm = m[k];
+        while (mm) {
+            s_vcol[off] = col[k] + __ffs(mm) - 1;
+            s_vrow[off] = p0 + pl;
+            ++off;
+            mm &= mm - 1u;
+        }
+    }
+    __syncthreads();
+    T yv[NX], xv[NX];
+#pragma unroll
+    for (int e = 0; e < NX; ++e) {
+        const int q = th + e * kWG;
+        const bool ok = q < nv;
+        yv[e] = ok ? ybar[s_vrow[q]] : T(0);
+        xv[e] = ok ? x[s_vcol[q]] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < NX; ++e) {
+        const int q = th + e * kWG;
+        if (q < nv) vbar[v0 + q] = yv[e] * xv[e];
+    }
+}
+
+template <typename T, int C>
+static hipError_t launch_vg_v(const spc5_matrix *A, const T *ybar, const T *x, T *vbar,
+                              hipStream_t s) {
+    hipLaunchKernelGGL((k_values_grad_v<T, C>), dim3((unsigned)A->ntiles_staged), dim3(kWG), 0,
+                       s, A->ntiles_staged, A->tile_p, A->tile_b, A->tile_v, A->tile_f,
+                       A->blk_ptr, A->blk_col, (const typename MaskOf<C>::type *)A->masks, ybar,
+                       x, vbar);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t vg_v_dispatch(const spc5_matrix *A, const void *ybar, const void *x,
+                                void *vbar, hipStream_t s) {
+    const T *yb = (const T *)ybar, *xx = (const T *)x;
+    if (A->c <= 4) return launch_vg_v<T, 4>(A, yb, xx, (T *)vbar, s);
+    if (A->c <= 8) return launch_vg_v<T, 8>(A, yb, xx, (T *)vbar, s);
+    return launch_vg_v<T, 16>(A, yb, xx, (T *)vbar, s);
+}
+
 hipError_t launch_values_grad(const spc5_matrix *A, const void *ybar, const void *x,
                               void *vbar, hipStream_t s) {
+    // beta(1,c) with a staged schedule: the value-mode kernel
+    if (A->r == 1 && A->tile_p && A->ntiles_staged > 0)
+        return A->dtype == SPC5_F64 ? vg_v_dispatch<double>(A, ybar, x, vbar, s)
+                                    : vg_v_dispatch<float>(A, ybar, x, vbar, s);
     return A->dtype == SPC5_F64 ? vg_dispatch<double>(A, ybar, x, vbar, s)
                                 : vg_dispatch<float>(A, ybar, x, vbar, s);
 }

@@ -552,6 +552,32 @@ def test_values_grad_bit_exact(A, rc, dev):
     assert np.array_equal(g.view(np.uint64), ref.view(np.uint64))
 
 
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("c", [3, 8, 16])
+@pytest.mark.parametrize("kernel", ["staged", "sweep"])
+def test_values_grad_r1_tiles(dtype, c, kernel, dev):
+    """beta(1,c) values gradient on the staged tile schedule (one workgroup
+    per tile), including piece tiles of rows longer than a tile and empty
+    rows; the same bits whichever forward kernel the matrix is set to.
+    FP32: the product of the two FP32-rounded factors, rounded once."""
+    A = long_rows_matrix(91 + c)
+    S = spc5()
+    say(f"values grad beta(1,{c}) {dtype} {kernel}")
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 1, c, dtype)
+    M.set_schedule(kernel)
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    w = np.random.default_rng(92).uniform(-1, 1, A.nrows)
+    g = M.values_grad(to_dev(w, dev, tdt), to_dev(A.x, dev, tdt)).cpu().numpy()
+    O = oracle.csr_to_spc5(A.rowptr, A.colidx, A.values, A.ncols, 1, c)
+    if dtype == "float64":
+        ref = oracle.spc5_values_grad(O, w, A.x)
+        assert np.array_equal(g.view(np.uint64), ref.view(np.uint64))
+    else:
+        ref = oracle.spc5_values_grad(O, w.astype(np.float32).astype(np.float64),
+                                      A.x.astype(np.float32).astype(np.float64))
+        assert np.array_equal(g, ref.astype(np.float32))
+
+
 def test_spmv_values_override(dev):
     A = W.laplacian_2d(30, seed=19)
     S = spc5()
