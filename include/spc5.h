@@ -126,6 +126,17 @@ int spc5_get_info(const spc5_matrix *A, spc5_info *out);
 int spc5_export(const spc5_matrix *A, int64_t *blk_ptr, int32_t *blk_col,
                 void *masks, void *values);
 
+/* The inverse conversion back to CSR (Section 2.4's format read the other
+ * way): for each panel, block, row of the block and set mask bit in
+ * ascending order, the entry (panel*r + row, anchor + bit, next packed
+ * value).  Inside one row the blocks' windows are disjoint and increasing,
+ * so each row comes out with its columns sorted; for a matrix made by
+ * csr_to_spc5 the result is the input CSR, bit for bit.  Host outputs:
+ * rowptr int64[nrows+1], colidx int32[nnz], values[nnz] of the matrix dtype;
+ * colidx or values may be NULL to skip them.  Synchronous.
+ * Errors: SPC5_EINVAL (NULL A or rowptr), SPC5_ENOMEM, SPC5_EDEVICE. */
+int spc5_to_csr(const spc5_matrix *A, int64_t *rowptr, int32_t *colidx, void *values);
+
 /* Forward-kernel choice.
  *  SPC5_KERNEL_STAGED: one wavefront per tile of consecutive panels; the
  *                     tile's packed values, masks and anchors are pulled into

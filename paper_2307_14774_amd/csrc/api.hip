@@ -291,6 +291,59 @@ int spc5_export(const spc5_matrix *A, int64_t *blk_ptr, int32_t *blk_col, void *
     return SPC5_OK;
 }
 
+int spc5_to_csr(const spc5_matrix *A, int64_t *rowptr, int32_t *colidx, void *values) {
+    if (!A) return fail(SPC5_EINVAL, "A is NULL");
+    if (!rowptr) return fail(SPC5_EINVAL, "rowptr is NULL");
+    const int r = A->r, vb = A->dtype == SPC5_F64 ? 8 : 4;
+    std::vector<int64_t> bp;
+    std::vector<int32_t> bc;
+    std::vector<uint16_t> mk;
+    std::vector<unsigned char> va;
+    try {
+        bp.resize((size_t)A->npanels + 1);
+        bc.resize((size_t)A->nblocks);
+        mk.resize((size_t)A->nblocks * r);
+        va.resize((size_t)A->nnz * vb);
+    } catch (...) {
+        return fail(SPC5_ENOMEM, "host allocation failed");
+    }
+    std::vector<uint8_t> mk8;
+    if (A->mask_bytes == 1) {
+        try {
+            mk8.resize(mk.size());
+        } catch (...) {
+            return fail(SPC5_ENOMEM, "host allocation failed");
+        }
+    }
+    int st = spc5_export(A, bp.data(), bc.data(),
+                         A->mask_bytes == 1 ? (void *)mk8.data() : (void *)mk.data(), va.data());
+    if (st != SPC5_OK) return st;
+    if (A->mask_bytes == 1)
+        for (size_t i = 0; i < mk.size(); ++i) mk[i] = mk8[i];
+    // per-row counts, then the entries row by row
+    std::fill(rowptr, rowptr + A->nrows + 1, (int64_t)0);
+    for (int64_t p = 0; p < A->npanels; ++p)
+        for (int64_t b = bp[p]; b < bp[p + 1]; ++b)
+            for (int i = 0; i < r; ++i)
+                if (p * r + i < A->nrows) rowptr[p * r + i + 1] += __builtin_popcount(mk[b * r + i]);
+    for (int64_t i = 0; i < A->nrows; ++i) rowptr[i + 1] += rowptr[i];
+    int64_t v = 0;    // next packed value
+    for (int64_t p = 0; p < A->npanels; ++p) {
+        int64_t at[8];
+        for (int i = 0; i < r; ++i) at[i] = p * r + i < A->nrows ? rowptr[p * r + i] : 0;
+        for (int64_t b = bp[p]; b < bp[p + 1]; ++b)
+            for (int i = 0; i < r; ++i)
+                for (unsigned m = mk[b * r + i]; m; m &= m - 1u) {
+                    const int k = __builtin_ctz(m);
+                    if (colidx) colidx[at[i]] = bc[b] + k;
+                    if (values) memcpy((unsigned char *)values + at[i] * vb, va.data() + v * vb, vb);
+                    ++at[i];
+                    ++v;
+                }
+    }
+    return SPC5_OK;
+}
+
 int spc5_set_schedule(spc5_matrix *A, int kernel, int ppt) {
     if (!A) return fail(SPC5_EINVAL, "A is NULL");
     if (kernel < SPC5_KERNEL_AUTO || kernel > SPC5_KERNEL_STAGED)

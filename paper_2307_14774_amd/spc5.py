@@ -22,7 +22,8 @@ STATUS = {0: "SPC5_OK", -1: "SPC5_EINVAL", -2: "SPC5_EBADCSR", -3: "SPC5_ENOMEM"
 
 # every symbol include/spc5.h declares
 EXPORTS = [
-    "csr_to_spc5", "spc5_free", "spc5_get_info", "spc5_export", "spc5_set_schedule",
+    "csr_to_spc5", "spc5_free", "spc5_get_info", "spc5_export", "spc5_to_csr",
+    "spc5_set_schedule",
     "spc5_set_variant",
     "spc5_spmv", "spc5_spmv_values", "spc5_spmv_transpose", "spc5_spmv_transpose_values",
     "spc5_prepare_transpose", "spc5_values_grad", "spc5_spmm", "spc5_batch_create", "spc5_batch_free",
@@ -69,6 +70,7 @@ def lib():
         L.spc5_free.restype = None
         L.spc5_get_info.argtypes = [P, ctypes.POINTER(spc5_info)]
         L.spc5_export.argtypes = [P, P, P, P, P]
+        L.spc5_to_csr.argtypes = [P, P, P, P]
         L.spc5_set_schedule.argtypes = [P, I, I]
         L.spc5_set_variant.argtypes = [P, I]
         L.spc5_spmv.argtypes = [P, P, P, P]
@@ -221,6 +223,16 @@ class Spc5Matrix:
         va = np.zeros(inf.nnz, dtype=np.float64 if inf.dtype == SPC5_F64 else np.float32)
         _check(lib().spc5_export(self._h, _np_ptr(bp), _np_ptr(bc), _np_ptr(mk), _np_ptr(va)))
         return bp, bc, mk, va
+
+    def to_csr(self):
+        """Host CSR (rowptr int64, colidx int32, values) read back from the
+        device arrays (the inverse conversion)."""
+        inf = self.info
+        rp = np.zeros(inf.nrows + 1, dtype=np.int64)
+        ci = np.zeros(inf.nnz, dtype=np.int32)
+        va = np.zeros(inf.nnz, dtype=np.float64 if inf.dtype == SPC5_F64 else np.float32)
+        _check(lib().spc5_to_csr(self._h, _np_ptr(rp), _np_ptr(ci), _np_ptr(va)))
+        return rp, ci, va
 
     # -- compute ----------------------------------------------------------
     def spmv(self, x, y=None, stream=None):

@@ -81,6 +81,7 @@ def test_null_out_and_null_handles():
     assert L.spc5_spmv(None, None, None, None) == -1
     assert L.spc5_spmv_transpose(None, None, None, None) == -1
     assert L.spc5_get_info(None, None) == -1
+    assert L.spc5_to_csr(None, None, None, None) == -1
     assert L.spc5_set_variant(None, 1) == -1
     assert L.spc5_prepare_transpose(None, 0, 0) == -1
     assert L.spc5_csr_spmv(None, None, None, None) == -1

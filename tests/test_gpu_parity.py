@@ -92,6 +92,27 @@ def test_conversion_bit_exact(A, rc, dev):
     assert np.array_equal(va.view(np.uint64), O.values.view(np.uint64))
 
 
+@pytest.mark.parametrize("A", CASES, ids=lambda a: a.name)
+@pytest.mark.parametrize("rc", [(1, 8), (2, 4), (4, 4), (3, 5), (8, 16), (1, 1)],
+                         ids=lambda t: "b%d_%d" % t)
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_to_csr_round_trip(A, rc, dtype, dev):
+    """spc5_to_csr reads the device arrays back as CSR: the input, bit for bit
+    (FP32: the input rounded to FP32), and equal to the oracle's inverse."""
+    r, c = rc
+    S = spc5()
+    say(f"to_csr {A.name} beta{rc} {dtype}")
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c, dtype)
+    rp, ci, va = M.to_csr()
+    assert np.array_equal(rp, A.rowptr)
+    assert np.array_equal(ci, A.colidx)
+    want = A.values if dtype == "float64" else A.values.astype(np.float32)
+    assert np.array_equal(va.view(np.uint8), want.view(np.uint8))
+    O = oracle.csr_to_spc5(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+    orp, oci, _ = oracle.spc5_to_csr(O)
+    assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+
+
 def long_rows_matrix(seed):
     """Rows at and past the one-thread walk's limit of 2048 nonzeros (2048,
     2049, 2111, 5000, 9999), with dense, sparse and run-and-gap columns, so
