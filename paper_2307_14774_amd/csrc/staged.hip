@@ -26,8 +26,9 @@
 // Tiles come from a schedule built at conversion (at most 256/r panels, VT
 // values and BT blocks per tile).  A panel larger than a tile is cut into
 // piece tiles spread over the grid (load balance for very long rows); their
-// partial row sums are added in tile order by a small fixup kernel.  No
-// atomics: results are reproducible bit for bit.
+// partial row sums are added in a fixed order by a small fixup kernel.  No
+// atomics: results are reproducible bit for bit.  Workgroups reach the XCDs in
+// runs of kXcdRun (xcd_chunks).
 #include "spc5_internal.h"
 #include "stage.h"
 #include "wave.h"
@@ -440,8 +441,7 @@ __global__ __launch_bounds__(kWG) void k_spmv_vstream(
 // are added in a fixed order by k_split_fixup, so the result stays
 // reproducible.  One thread per group; pass 0 counts the tiles and the split
 // panels of each group, pass 1 writes them.
-template <typename MT>
-__global__ void k_tile_groups(int pass, int64_t npanels, int r, int ppw, int vt, int bt,
+__global__ void k_tile_groups(int pass, int64_t npanels, int ppw, int vt, int bt,
                               const int32_t *bp, const int32_t *pv, const int64_t *vpre,
                               int64_t *count, const int64_t *first, int64_t *scount,
                               const int64_t *sfirst, int32_t *tp, int32_t *tb, int32_t *tv,
@@ -540,15 +540,14 @@ __global__ __launch_bounds__(256) void k_split_fixup(int64_t nsplit, int r, int6
     if (lane == 0) y[row] = acc;
 }
 
-template <typename MT>
 static void launch_tile_groups(unsigned grid, int pass, const spc5_matrix *A, int ppw, int vt,
                                int bt, const int64_t *vpre, int64_t *count, const int64_t *first,
                                int64_t *scount, const int64_t *sfirst, int32_t *tp, int32_t *tb,
                                int32_t *tv, int32_t *tf, int32_t *sp, int32_t *st0, int32_t *st1,
                                int *maxvals) {
-    hipLaunchKernelGGL(k_tile_groups<MT>, dim3(grid), dim3(256), 0, nullptr, pass, A->npanels,
-                       A->r, ppw, vt, bt, A->blk_ptr, A->panel_val, vpre, count, first, scount,
-                       sfirst, tp, tb, tv, tf, sp, st0, st1, maxvals);
+    hipLaunchKernelGGL(k_tile_groups, dim3(grid), dim3(256), 0, nullptr, pass, A->npanels, ppw,
+                       vt, bt, A->blk_ptr, A->panel_val, vpre, count, first, scount, sfirst, tp,
+                       tb, tv, tf, sp, st0, st1, maxvals);
 }
 
 // flag = 1 when some panel is longer than a tile (vt values or bt blocks).
@@ -649,14 +648,8 @@ int build_staged_schedule(spc5_matrix *A, int ppw_req, bool alone) {
             (e = excl_scan_i64(bcnt, nb, vpre, s, &scratch3)) != hipSuccess)
             return bail(e, "counting block values");
     }
-    if (m8)
-        launch_tile_groups<uint8_t>(grid, 0, A, ppw, vt, bt, vpre, count, nullptr, scount,
-                                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                    nullptr, nullptr, maxv);
-    else
-        launch_tile_groups<uint16_t>(grid, 0, A, ppw, vt, bt, vpre, count, nullptr, scount,
-                                     nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                     nullptr, nullptr, maxv);
+    launch_tile_groups(grid, 0, A, ppw, vt, bt, vpre, count, nullptr, scount, nullptr, nullptr,
+                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, maxv);
     if ((e = hipGetLastError()) != hipSuccess ||
         (e = excl_scan_i64(count, ng, first, s, &scratch)) != hipSuccess ||
         (e = excl_scan_i64(scount, ng, sfirst, s, &scratch2)) != hipSuccess)
@@ -682,14 +675,9 @@ int build_staged_schedule(spc5_matrix *A, int ppw_req, bool alone) {
         (nsplit > 0 &&
          (e = hipMalloc(&A->partial, nt1 * (size_t)A->r * vb)) != hipSuccess))
         return bail(e, "allocating the tile schedule");
-    if (m8)
-        launch_tile_groups<uint8_t>(grid, 1, A, ppw, vt, bt, vpre, nullptr, first, nullptr,
-                                    sfirst, A->tile_p, A->tile_b, A->tile_v, A->tile_f,
-                                    A->split_p, A->split_t0, A->split_t1, maxv);
-    else
-        launch_tile_groups<uint16_t>(grid, 1, A, ppw, vt, bt, vpre, nullptr, first, nullptr,
-                                     sfirst, A->tile_p, A->tile_b, A->tile_v, A->tile_f,
-                                     A->split_p, A->split_t0, A->split_t1, maxv);
+    launch_tile_groups(grid, 1, A, ppw, vt, bt, vpre, nullptr, first, nullptr, sfirst, A->tile_p,
+                       A->tile_b, A->tile_v, A->tile_f, A->split_p, A->split_t0, A->split_t1,
+                       maxv);
     hipLaunchKernelGGL(k_tile_sentinel, dim3(1), dim3(1), 0, s, np, ntiles, A->blk_ptr,
                        A->panel_val, A->tile_p, A->tile_b, A->tile_v, A->tile_f);
     int hmax = 0;
