@@ -198,7 +198,10 @@ int spc5_spmv_values(const spc5_matrix *A, const void *values, const void *x,
  * NULL for the matrix's own.  Device pointers.
  * Without a plan: masked scatter from A's blocks (each set mask bit adds
  * value * ybar[row] to xbar[anchor+k] with a float atomic; xbar is zeroed on
- * the stream first); the accumulation order varies between runs.
+ * the stream first); the accumulation order varies between runs.  When some
+ * column holds thousands of entries (sampled at conversion) the
+ * contributions are first summed per workgroup in LDS, so a popular column
+ * takes one atomic per workgroup rather than one per row.
  * With a plan (spc5_prepare_transpose): the forward kernel over the stored
  * A^T; no atomics, the result is reproducible bit for bit.  When `values` is
  * given, the plan first moves them to A^T's order (two passes through

@@ -102,6 +102,102 @@ __global__ __launch_bounds__(kWave) void k_values_grad(
     }
 }
 
+// The same scatter with hot-column pre-aggregation.  A workgroup of four
+// wavefronts walks a contiguous range of tiles (one tile per wavefront at a
+// time) and adds its contributions into an LDS table of kAggSlots columns
+// (two probes, slot claimed by the first column that reaches it); a column
+// that finds both probes taken goes straight to a global atomic.  At the end
+// every occupied slot issues one global atomic.  A column shared by many rows
+// (a popular node of a graph) then costs one global atomic per workgroup
+// instead of one per row.
+constexpr int kAggSlots = 2048;
+constexpr int kAggGrid = 2048;
+
+template <typename T>
+__device__ __forceinline__ void agg_add(int *tag, T *acc, int col, T v, T *xbar) {
+    const int s0 = (int)(((unsigned)col * 2654435761u) >> 21) & (kAggSlots - 1);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const int sl = s0 ^ p;
+        int t = tag[sl];
+        if (t == -1) {
+            const int old = atomicCAS(&tag[sl], -1, col);
+            t = old == -1 ? col : old;
+        }
+        if (t == col) {
+            atomicAdd(&acc[sl], v);
+            return;
+        }
+    }
+    atomicAdd(&xbar[col], v);
+}
+
+template <typename T, int R, int C>
+__global__ __launch_bounds__(256) void k_transpose_agg(
+    int64_t npanels, int ppt, int64_t ntiles, int64_t tpw,
+    const int32_t *__restrict__ blk_ptr, const int32_t *__restrict__ blk_col,
+    const typename MaskOf<C>::type *__restrict__ masks, const T *__restrict__ val,
+    const int32_t *__restrict__ panel_val, const T *__restrict__ ybar, T *__restrict__ xbar)
+{
+    constexpr int BPS = kWave / R;
+    constexpr int LANES = BPS * R;
+    constexpr bool kGroup = R > 1 && (R & (R - 1)) == 0;
+    __shared__ int s_tag[kAggSlots];
+    __shared__ T s_acc[kAggSlots];
+    const int th = threadIdx.x, lane = lane_id(), wv = th / kWave;
+    for (int q = th; q < kAggSlots; q += 256) {
+        s_tag[q] = -1;
+        s_acc[q] = T(0);
+    }
+    __syncthreads();
+    const int64_t t0 = (int64_t)blockIdx.x * tpw;
+    const int64_t t1 = min(t0 + tpw, ntiles);
+    const int i = lane % R;
+    const int bl = lane / R;
+    for (int64_t tile = t0 + wv; tile < t1; tile += 256 / kWave) {
+        const TileCtx t = tile_begin(tile, ppt, npanels, blk_ptr);
+        int vbase = panel_val[t.p0];
+        for (int bs = t.b0; bs < t.b1; bs += BPS) {
+            const int b = bs + bl;
+            const bool act = (lane < LANES) && (b < t.b1);
+            const unsigned m = act ? (unsigned)masks[(int64_t)b * R + i] : 0u;
+            const int col0 = act ? blk_col[b] : 0;
+            const int cnt = __popc(m);
+            const int incl = wave_incl_scan(cnt);
+            int j = vbase + incl - cnt;
+            vbase += __shfl(incl, kWave - 1);
+            const int pid = tile_panel_of(b, t.pe);
+            const T yv = m ? ybar[(t.p0 + pid) * R + i] : T(0);
+            if constexpr (kGroup) {
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    const bool has = (m >> k) & 1u;
+                    T contrib = has ? val[j] * yv : T(0);
+                    j += has ? 1 : 0;
+                    unsigned any = has ? 1u : 0u;
+#pragma unroll
+                    for (int d = 1; d < R; d <<= 1) {
+                        contrib += __shfl_xor(contrib, d);
+                        any |= __shfl_xor(any, d);
+                    }
+                    if (any && i == (k % R)) agg_add(s_tag, s_acc, col0 + k, contrib, xbar);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < C; ++k) {
+                    if ((m >> k) & 1u) {
+                        agg_add(s_tag, s_acc, col0 + k, val[j] * yv, xbar);
+                        ++j;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = th; q < kAggSlots; q += 256)
+        if (s_tag[q] >= 0) atomicAdd(&xbar[s_tag[q]], s_acc[q]);
+}
+
 template <typename T, int R, int C>
 static hipError_t launch_tr(const spc5_matrix *A, const T *val, const T *ybar, T *xbar,
                             hipStream_t s) {
@@ -109,10 +205,21 @@ static hipError_t launch_tr(const spc5_matrix *A, const T *val, const T *ybar, T
     if (e != hipSuccess) return e;
     const int64_t ntiles = (A->npanels + A->ppt - 1) / A->ppt;
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_transpose<T, R, C>), dim3((unsigned)ntiles), dim3(kWave), 0, s,
-                       A->npanels, A->nrows, A->ppt, ntiles, A->blk_ptr, A->blk_col,
-                       (const typename MaskOf<C>::type *)A->masks, val, A->panel_val, ybar,
-                       xbar);
+    // aggregation pays where columns are shared by many rows; a banded
+    // matrix's columns are short and go straight to global atomics
+    if (A->hot_cols) {
+        const int64_t tpw = (ntiles + kAggGrid - 1) / kAggGrid;
+        const int64_t grid = (ntiles + tpw - 1) / tpw;
+        hipLaunchKernelGGL((k_transpose_agg<T, R, C>), dim3((unsigned)grid), dim3(256), 0, s,
+                           A->npanels, A->ppt, ntiles, tpw, A->blk_ptr, A->blk_col,
+                           (const typename MaskOf<C>::type *)A->masks, val, A->panel_val, ybar,
+                           xbar);
+    } else {
+        hipLaunchKernelGGL((k_transpose<T, R, C>), dim3((unsigned)ntiles), dim3(kWave), 0, s,
+                           A->npanels, A->nrows, A->ppt, ntiles, A->blk_ptr, A->blk_col,
+                           (const typename MaskOf<C>::type *)A->masks, val, A->panel_val, ybar,
+                           xbar);
+    }
     return hipGetLastError();
 }
 

@@ -217,6 +217,19 @@ __global__ void k_narrow(int64_t npanels, int64_t nrows, int r, const int64_t *b
     pval[p] = (int32_t)rowptr[row];
 }
 
+// Every kColSample-th nonzero counted by column: a column with many entries
+// (a popular node of a graph) reaches kHotSamples counts when it holds about
+// kColSample*kHotSamples of them, and then raises the flag (once per column,
+// so the flag itself sees no contention).
+constexpr int64_t kColSample = 64;
+constexpr int kHotSamples = 64;
+
+__global__ void k_col_sample(int64_t nnz, const int32_t *__restrict__ colidx, int *cnt,
+                             int *flag) {
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kColSample;
+    if (k < nnz && atomicAdd(&cnt[colidx[k]], 1) + 1 == kHotSamples) *flag = 1;
+}
+
 __global__ void k_max(const int64_t *in, int64_t n, unsigned long long *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) atomicMax(out, (unsigned long long)in[i]);
@@ -348,6 +361,30 @@ int convert_on_device(spc5_matrix *A, const int64_t *d_rowptr, const int32_t *d_
         return hip_fail(e, "reading the block count");
     }
     A->max_panel_blocks = (int64_t)maxb;
+    // columns with thousands of entries: the atomic transpose aggregates them
+    A->hot_cols = false;
+    const int64_t nnz = A->nnz;
+    if (nnz >= kColSample * kHotSamples && A->ncols > 0) {
+        int *cnt = nullptr;
+        int hot = 0;
+        const int64_t ns = (nnz + kColSample - 1) / kColSample;
+        if ((e = hipMalloc((void **)&cnt, (size_t)(A->ncols + 1) * 4)) != hipSuccess ||
+            (e = zero_fill(cnt, A->ncols + 1, 4, s)) != hipSuccess) {
+            if (cnt) (void)hipFree(cnt);
+            cleanup();
+            return hip_fail(e, "sampling column lengths");
+        }
+        hipLaunchKernelGGL(k_col_sample, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, nnz,
+                           d_colidx, cnt, cnt + A->ncols);
+        if ((e = hipGetLastError()) != hipSuccess ||
+            (e = hipMemcpy(&hot, cnt + A->ncols, 4, hipMemcpyDeviceToHost)) != hipSuccess) {
+            (void)hipFree(cnt);
+            cleanup();
+            return hip_fail(e, "sampling column lengths");
+        }
+        (void)hipFree(cnt);
+        A->hot_cols = hot != 0;
+    }
     if (nblocks >= ((int64_t)1 << 31)) {
         cleanup();
         return fail(SPC5_EUNSUPPORTED, "nblocks = %lld does not fit int32 device indices",

@@ -454,6 +454,31 @@ def test_transpose(A, rc, dev):
     assert np.all(np.abs(xb - ref) <= g * absum)
 
 
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("rc", [(1, 8), (2, 4), (4, 4), (3, 5)], ids=lambda t: "b%d_%d" % t)
+def test_transpose_hot_columns(rc, dtype, dev):
+    """Atomic transpose (no plan) of a graph whose first columns are in almost
+    every row: contributions are summed per workgroup in LDS before the global
+    atomics.  Against the oracle's CSR transpose with the per-column bound."""
+    A = W.zipf_graph(1 << 14, seed=11)
+    assert np.bincount(A.colidx).max() > 8192
+    S = spc5()
+    say(f"transpose hot columns beta{rc} {dtype}")
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, *rc, dtype)
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    w = np.random.default_rng(12).uniform(-1, 1, A.nrows)
+    xb = M.transpose(to_dev(w, dev, tdt)).cpu().double().numpy()
+    v, wr = (A.values, w) if dtype == "float64" else (
+        A.values.astype(np.float32).astype(np.float64), w.astype(np.float32).astype(np.float64))
+    ref = oracle.csr_spmv_t(A.rowptr, A.colidx, v, wr, A.ncols)
+    absum = oracle.csr_spmv_t(A.rowptr, A.colidx, np.abs(v), np.abs(wr), A.ncols)
+    ncol = np.bincount(A.colidx, minlength=A.ncols).astype(np.float64)
+    u = 2.0 ** -52 if dtype == "float64" else 2.0 ** -23
+    g = (ncol + 1) * u / (1 - (ncol + 1) * u)
+    assert np.all(np.abs(xb - ref) <= g * absum)
+    assert oracle.rel_l2(xb, ref) <= (1e-14 if dtype == "float64" else 1e-6)
+
+
 @pytest.mark.parametrize("A", CASES, ids=lambda a: a.name)
 @pytest.mark.parametrize("rc,trc", [((1, 8), (0, 0)), ((2, 4), (0, 0)), ((4, 4), (0, 0)),
                                     ((3, 5), (4, 4)), ((8, 16), (1, 8)), ((4, 4), (2, 8)),
