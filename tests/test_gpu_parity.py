@@ -675,3 +675,85 @@ def test_binding_rejects_wrong_tensors(dev):
         M.spmv(torch.zeros(11, dtype=torch.float64, device=dev))
     with pytest.raises(TypeError):
         M.spmv(torch.zeros(12, dtype=torch.float64))
+
+
+# ------------------------------------------------------------ streams and graphs
+
+def test_spmv_two_streams(dev):
+    """One handle, products issued on two streams at once (allowed for a matrix
+    without split panels: the handle is read-only then); every result equals
+    the eager single-stream product bit for bit."""
+    A = W.laplacian_2d(64, seed=31)
+    S = spc5()
+    say("spmv on two streams")
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 4, 4)
+    assert M.info.split_panels == 0
+    rng = np.random.default_rng(32)
+    xs = [to_dev(rng.uniform(-1, 1, A.ncols), dev) for _ in range(8)]
+    want = [M.spmv(x).clone() for x in xs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    ys = [torch.full((A.nrows,), float("nan"), dtype=torch.float64, device=dev) for _ in xs]
+    for st in streams:
+        st.wait_stream(torch.cuda.current_stream())
+    for q, (x, y) in enumerate(zip(xs, ys)):
+        with torch.cuda.stream(streams[q % 2]):
+            M.spmv(x, y, stream=streams[q % 2])
+    torch.cuda.synchronize()
+    for q in range(len(xs)):
+        assert torch.equal(ys[q], want[q]), q
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_graph_replay_forward_and_backward(dtype, dev):
+    """A HIP graph holding the forward, the transposed product through the plan
+    with caller values theta (value move, piece tiles of hub rows and their
+    fixup) and the values gradient, replayed with new inputs written eagerly
+    between replays: every replay equals the eager calls bit for bit."""
+    A = W.zipf_graph(1 << 12, seed=33)
+    S = spc5()
+    say(f"graph replay forward+backward {dtype}")
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 1, 8, dtype)
+    M.prepare_transpose(1, 8)
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    rng = np.random.default_rng(34)
+    x = to_dev(rng.uniform(-1, 1, A.ncols), dev, tdt)
+    w = to_dev(rng.uniform(-1, 1, A.nrows), dev, tdt)
+    th = to_dev(rng.uniform(-1, 1, A.nnz), dev, tdt)
+    y = torch.empty(A.nrows, dtype=tdt, device=dev)
+    xb = torch.empty(A.ncols, dtype=tdt, device=dev)
+    vb = torch.empty(A.nnz, dtype=tdt, device=dev)
+
+    def step(stream=None):
+        M.spmv_values(th, x, y, stream=stream)
+        M.transpose(w, xb, values=th, stream=stream)
+        M.values_grad(w, x, vb, stream=stream)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step(side)                         # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for t_ in (x, w, th):
+            t_.copy_(to_dev(rng.uniform(-1, 1, t_.numel()), dev, tdt))
+        for o in (y, xb, vb):
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = [o.clone() for o in (y, xb, vb)]
+        for o in (y, xb, vb):
+            o.fill_(float("nan"))
+        step()
+        torch.cuda.synchronize()
+        for a, b in zip(got, (y, xb, vb)):
+            assert torch.equal(a, b), rep
+        # and against the oracle (theta in packed order = CSR order for beta(1,8))
+        ref = oracle.csr_spmv(A.rowptr, A.colidx, th.double().cpu().numpy(), x.double().cpu().numpy())
+        assert oracle.rel_l2(got[0].double().cpu().numpy(), ref) <= (1e-14 if dtype == "float64" else 1e-6)
