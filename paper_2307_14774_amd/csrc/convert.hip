@@ -221,13 +221,18 @@ __global__ void k_narrow(int64_t npanels, int64_t nrows, int r, const int64_t *b
 // (a popular node of a graph) reaches kHotSamples counts when it holds about
 // kColSample*kHotSamples of them, and then raises the flag (once per column,
 // so the flag itself sees no contention).
+// The counters are at most kColBuckets, columns folded onto them by
+// remainder: a fold can only add a false alarm (the aggregating transpose is
+// then used where it was not needed, still correct), and with fewer than 2^31
+// nonzeros no bucket of a uniform matrix comes near kHotSamples.
 constexpr int64_t kColSample = 64;
 constexpr int kHotSamples = 64;
+constexpr int64_t kColBuckets = 1 << 20;
 
-__global__ void k_col_sample(int64_t nnz, const int32_t *__restrict__ colidx, int *cnt,
-                             int *flag) {
+__global__ void k_col_sample(int64_t nnz, const int32_t *__restrict__ colidx, int nbuckets,
+                             int *cnt, int *flag) {
     const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kColSample;
-    if (k < nnz && atomicAdd(&cnt[colidx[k]], 1) + 1 == kHotSamples) *flag = 1;
+    if (k < nnz && atomicAdd(&cnt[colidx[k] % nbuckets], 1) + 1 == kHotSamples) *flag = 1;
 }
 
 __global__ void k_max(const int64_t *in, int64_t n, unsigned long long *out) {
@@ -368,16 +373,17 @@ int convert_on_device(spc5_matrix *A, const int64_t *d_rowptr, const int32_t *d_
         int *cnt = nullptr;
         int hot = 0;
         const int64_t ns = (nnz + kColSample - 1) / kColSample;
-        if ((e = hipMalloc((void **)&cnt, (size_t)(A->ncols + 1) * 4)) != hipSuccess ||
-            (e = zero_fill(cnt, A->ncols + 1, 4, s)) != hipSuccess) {
+        const int nbk = (int)std::min<int64_t>(A->ncols, kColBuckets);
+        if ((e = hipMalloc((void **)&cnt, (size_t)(nbk + 1) * 4)) != hipSuccess ||
+            (e = zero_fill(cnt, nbk + 1, 4, s)) != hipSuccess) {
             if (cnt) (void)hipFree(cnt);
             cleanup();
             return hip_fail(e, "sampling column lengths");
         }
         hipLaunchKernelGGL(k_col_sample, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, nnz,
-                           d_colidx, cnt, cnt + A->ncols);
+                           d_colidx, nbk, cnt, cnt + nbk);
         if ((e = hipGetLastError()) != hipSuccess ||
-            (e = hipMemcpy(&hot, cnt + A->ncols, 4, hipMemcpyDeviceToHost)) != hipSuccess) {
+            (e = hipMemcpy(&hot, cnt + nbk, 4, hipMemcpyDeviceToHost)) != hipSuccess) {
             (void)hipFree(cnt);
             cleanup();
             return hip_fail(e, "sampling column lengths");
