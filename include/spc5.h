@@ -138,28 +138,36 @@ int spc5_export(const spc5_matrix *A, int64_t *blk_ptr, int32_t *blk_col,
 int spc5_to_csr(const spc5_matrix *A, int64_t *rowptr, int32_t *colidx, void *values);
 
 /* Forward-kernel choice.
- *  SPC5_KERNEL_STAGED: one wavefront per tile of consecutive panels; the
- *                     tile's packed values, masks and anchors are pulled into
- *                     LDS with 16-byte coalesced loads, a wavefront scan gives
- *                     every block its value offset, then lanes walk the rows
- *                     of the tile (split over sub-lanes for long panels)
- *                     and gather x.  The default.
+ *  SPC5_KERNEL_STAGED: a 256-thread workgroup walks 1-8 consecutive tiles of
+ *                     a schedule built at conversion (tiles capped by values
+ *                     and blocks; a panel longer than a tile is cut into
+ *                     pieces summed by a small fixup); each tile's packed
+ *                     values, masks and anchors are pulled into LDS with
+ *                     16-byte loads while the next tile's are in flight, a
+ *                     workgroup scan gives every block its value offset;
+ *                     r > 1: one thread per block gathers its x window
+ *                     (Section 3.1's single load), rows are summed by
+ *                     sub-lanes and a butterfly; r = 1: one x load per
+ *                     nonzero from the decoded columns.  The default
+ *                     whenever x fits a 2 GiB buffer.
  *  SPC5_KERNEL_ROWS:  one lane per panel row; the lane walks the blocks of
  *                     its panel (r lanes share a panel), no cross-lane
  *                     reduction.  Best for short and regular panels.
  *  SPC5_KERNEL_SWEEP: one wavefront per tile of consecutive panels, one lane
  *                     per block row, segmented wavefront reduction.  Handles
  *                     panels of any length evenly.
- *  SPC5_KERNEL_AUTO:  chosen at conversion from the panel length statistics. */
+ *  SPC5_KERNEL_AUTO:  STAGED when x fits a 2 GiB buffer, SWEEP otherwise. */
 typedef enum {
     SPC5_KERNEL_AUTO = 0, SPC5_KERNEL_ROWS = 1, SPC5_KERNEL_SWEEP = 2, SPC5_KERNEL_STAGED = 3
 } spc5_kernel;
 
 /* Schedule of the forward product: kernel choice and, for the sweep and
- * staged kernels, the number of consecutive panels one wavefront handles
- * (1..64, at most 64/r for the staged kernel; 0 = default from the mean panel
- * length).  Not safe to call while compute calls
- * on A are in flight. */
+ * staged kernels, a cap on the consecutive panels of one tile (1..64; the
+ * staged kernel also stops at 256/r; 0 = default: the mean panel length for
+ * the sweep kernel, the value and block caps alone for the staged kernel).
+ * Not safe to call while compute calls on A are in flight.
+ * Errors: SPC5_EINVAL (NULL A, unknown kernel, cap out of range),
+ * SPC5_EUNSUPPORTED (staged or rows kernel with x above 2 GiB). */
 int spc5_set_schedule(spc5_matrix *A, int kernel, int panels_per_tile);
 
 /* Kernel variants of the staged forward product that reproduce the paper's
