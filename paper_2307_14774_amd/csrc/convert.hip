@@ -89,30 +89,46 @@ __global__ __launch_bounds__(256) void k_block_long_rows(
     int64_t nb = 0, anchor = 0, lim = INT64_MIN;
     unsigned m = 0;
     bool open = false;
-    for (int64_t base = b; base < e; base += kWave) {
-        const int64_t k = base + lane;
-        const bool valid = k < e;
-        const int64_t x = valid ? (int64_t)colidx[k] : INT64_MAX;
-        if (FILL && valid) vout[k] = vin[k];
-        uint64_t pend = __ballot(valid);
-        while (pend) {
-            const uint64_t cov = __ballot(valid && x < lim) & pend;
-            unsigned bit = ((cov >> lane) & 1ull) ? 1u << (unsigned)(x - anchor) : 0u;
-            for (int d = 1; d < kWave; d <<= 1) bit |= __shfl_xor(bit, d);
-            m |= bit;
-            pend &= ~cov;
-            if (pend) {
-                if (open) {
-                    if (FILL && lane == 0) {
-                        bcol[first + nb] = (int32_t)anchor;
-                        masks[first + nb] = (MT)m;
-                    }
-                    ++nb;
+    // kLongGroup chunks of 64 columns are loaded together, so one memory
+    // latency is paid per group rather than per chunk
+    constexpr int kLongGroup = 8;
+    for (int64_t gbase = b; gbase < e; gbase += kWave * kLongGroup) {
+        int64_t xg[kLongGroup];
+        T vg[kLongGroup];
+#pragma unroll
+        for (int q = 0; q < kLongGroup; ++q) {
+            const int64_t k = gbase + q * kWave + lane;
+            xg[q] = k < e ? (int64_t)colidx[k] : INT64_MAX;
+            if (FILL) vg[q] = k < e ? vin[k] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < kLongGroup; ++q) {
+            const int64_t k = gbase + q * kWave + lane;
+            const bool valid = k < e;
+            const int64_t x = xg[q];
+            if (FILL && valid) vout[k] = vg[q];
+            uint64_t pend = __ballot(valid);
+            while (pend) {
+                const uint64_t cov = __ballot(valid && x < lim) & pend;
+                if (FILL) {
+                    unsigned bit = ((cov >> lane) & 1ull) ? 1u << (unsigned)(x - anchor) : 0u;
+                    for (int d = 1; d < kWave; d <<= 1) bit |= __shfl_xor(bit, d);
+                    m |= bit;
                 }
-                anchor = __shfl(x, __ffsll((unsigned long long)pend) - 1);
-                lim = anchor + c;
-                m = 0;
-                open = true;
+                pend &= ~cov;
+                if (pend) {
+                    if (open) {
+                        if (FILL && lane == 0) {
+                            bcol[first + nb] = (int32_t)anchor;
+                            masks[first + nb] = (MT)m;
+                        }
+                        ++nb;
+                    }
+                    anchor = __shfl(x, __ffsll((unsigned long long)pend) - 1);
+                    lim = anchor + c;
+                    m = 0;
+                    open = true;
+                }
             }
         }
     }
