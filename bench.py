@@ -9,11 +9,14 @@ stream, x gather, FMA, row reduction and y store) of one seeded synthetic
 matrix already resident in HBM.  The default workload is the 5-point
 Laplacian on a 2048 x 2048 grid in FP64 with beta(4,4).  One JSON line is
 printed: GFLOP/s (2 flops per stored nonzero), the roofline of the forward
-kernel (algorithmic bytes / measured launch time against 8 TB/s), the other
+kernel (algorithmic bytes / mean launch time against 8 TB/s), the other
 formats and the plain CSR kernel on the same GPU, the FEM matrix in FP64 and
 FP32, the differentiated product (forward + backward) on the 2^20 Zipf graph,
 the batched SpMM over 256 uneven matrices, and the CPU oracle timed on this
-host as a baseline.
+host as a baseline.  Launch times are means over back-to-back launches
+between one HIP event pair on the launching stream (gaps between launches
+included); the cold-cache run alone puts an event pair around every launch,
+so that the flush between launches stays outside the events.
 
 Profiling helpers (host only, no GPU):
     python bench.py --traffic-from FETCH.csv WRITE.csv
@@ -93,6 +96,27 @@ def time_launches(fn, steps, warmup, flush=None):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     return t1 - t0, [a.elapsed_time(b) for a, b in ev]
+
+
+def time_region(fn, steps, warmup):
+    """Run fn() `warmup` times, then `steps` times back to back between one
+    HIP event pair on the current stream (the stream the kernels run on).
+    Returns (wall seconds of the timed region, mean ms per launch): the
+    launches' own durations plus the gaps between consecutive launches."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return t1 - t0, a.elapsed_time(b) / steps
 
 
 def traffic_from_profiles(workload_tag):
@@ -207,8 +231,7 @@ def fem_extras(dev):
         for rc in shapes:
             log(f"FEM {dt} beta{rc}")
             M = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, *rc, dt)
-            _, ms = time_launches(lambda: M.spmv(x, y), 30, 5)
-            avg = float(np.mean(ms)) * 1e-3
+            avg = time_region(lambda: M.spmv(x, y), 30, 5)[1] * 1e-3
             nb = M.info.spmv_bytes
             res[f"{dt} beta({rc[0]},{rc[1]})"] = {
                 "gflops": round(2.0 * A.nnz / avg / 1e9, 1), "launch_us": round(avg * 1e6, 1),
@@ -220,8 +243,7 @@ def fem_extras(dev):
     C = spc5.CsrMatrix(A.rowptr, A.colidx, A.values, A.ncols)
     x = torch.from_numpy(A.x).to(dev)
     y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
-    _, ms = time_launches(lambda: C.spmv(x, y), 30, 5)
-    avg = float(np.mean(ms)) * 1e-3
+    avg = time_region(lambda: C.spmv(x, y), 30, 5)[1] * 1e-3
     res["float64 csr"] = {"gflops": round(2.0 * A.nnz / avg / 1e9, 1),
                           "launch_us": round(avg * 1e6, 1),
                           "gbs": round(C.spmv_bytes / avg / 1e9, 1),
@@ -229,11 +251,6 @@ def fem_extras(dev):
                           "rel_l2_vs_fp64_oracle": oracle.rel_l2(y.cpu().numpy(), yref)}
     C.free()
     return res
-
-
-def _avg_us(ms):
-    import numpy as np
-    return float(np.mean(ms)) * 1e3
 
 
 def backward_extras(dev):
@@ -270,8 +287,7 @@ def backward_extras(dev):
     res = {"nrows": G.nrows, "nnz": G.nnz, "beta": [r, c], "fill": round(M.info.fill, 4),
            "dtype": "f32"}
     def timed(fn, n=30):
-        _, ms = time_launches(fn, n, 5)
-        us = _avg_us(ms)
+        us = time_region(fn, n, 5)[1] * 1e3
         return {"launch_us": round(us, 2), "gbs": round(nb / us / 1e3, 1),
                 "frac_hbm": round(nb / us / 1e3 / PEAK_HBM_GBS, 4)}
     res["forward"] = timed(lambda: M.spmv_values(theta, x, y))
@@ -298,8 +314,7 @@ def backward_extras(dev):
         th.grad = None
         xx.grad = None
         (spc5_matvec(M, th, xx) * ybar).sum().backward()
-    _, ms = time_launches(step, 10, 3)
-    res["autograd_step_us"] = round(_avg_us(ms), 1)
+    res["autograd_step_us"] = round(time_region(step, 10, 3)[1] * 1e3, 1)
     # parity
     O = oracle.csr_to_spc5(G.rowptr, G.colidx, theta_h.astype(np.float64), G.ncols, r, c)
     M.transpose(ybar, xbar, values=theta)
@@ -315,8 +330,8 @@ def backward_extras(dev):
     C = spc5.CsrMatrix(G.rowptr, G.colidx, G.values, G.ncols)
     x64 = torch.from_numpy(G.x).to(dev)
     y64 = torch.empty(G.nrows, dtype=torch.float64, device=dev)
-    _, ms = time_launches(lambda: C.spmv(x64, y64), 30, 5)
-    res["csr_fp64_forward_us"] = round(_avg_us(ms), 2)
+    us_csr = time_region(lambda: C.spmv(x64, y64), 30, 5)[1] * 1e3
+    res["csr_fp64_forward_us"] = round(us_csr, 2)
     res["speedup_fwd_vs_csr_fp64"] = round(res["csr_fp64_forward_us"]
                                            / res["forward"]["launch_us"], 3)
     res["fwd_bwd_vs_3x_csr_fp64"] = round(3 * res["csr_fp64_forward_us"] / res["fwd_bwd_us"], 3)
@@ -350,8 +365,7 @@ def batch_extras(dev, nmat=256, ks=(1, 4, 16)):
     def plain_csr():
         for C, x, y in zip(csrs, xs, ys):
             C.spmv(x, y)
-    _, ms = time_launches(plain_csr, 5, 2)
-    plain_csr_us = _avg_us(ms)
+    plain_csr_us = time_region(plain_csr, 5, 2)[1] * 1e3
     res["plain_fp64_csr_us_per_vector"] = round(plain_csr_us, 1)
     for C in csrs:
         C.free()
@@ -370,8 +384,8 @@ def batch_extras(dev, nmat=256, ks=(1, 4, 16)):
             def plain_spc5():
                 for M, x, y in zip(Ms, xs, ys):
                     M.spmv(x, y)
-            _, ms = time_launches(plain_spc5, 5, 2)
-            res["plain_fp64_spc5_us_per_vector"] = round(_avg_us(ms), 1)
+            us_plain = time_region(plain_spc5, 5, 2)[1] * 1e3
+            res["plain_fp64_spc5_us_per_vector"] = round(us_plain, 1)
         B = spc5.Spc5Batch(Ms)
         for k in ks:
             log(f"batch: {dt} k={k}")
@@ -380,8 +394,7 @@ def batch_extras(dev, nmat=256, ks=(1, 4, 16)):
             Xs = [torch.from_numpy(X).to(dev, tdt) for X in Xh]
             Ys = [torch.empty((A.nrows, k), dtype=tdt, device=dev) for A in mats]
             B.set_operands(Xs, Ys)
-            _, ms = time_launches(B.run, 10, 3)
-            us = _avg_us(ms)
+            us = time_region(B.run, 10, 3)[1] * 1e3
             vb = 8 if dt == "float64" else 4
             # matrix streamed once per launch + k vectors in and out
             byts = sum(M.info.spmv_bytes - vb * (A.ncols + A.nrows) + k * vb * (A.ncols + A.nrows)
@@ -434,8 +447,7 @@ def ablation_extras(dev, A_lap):
             "dense_2048": W.dense(2048, seed=3), "random10k": W.random_uniform(10_000, 10, seed=0)}
 
     def one(M, x, y, n=20):
-        _, ms = time_launches(lambda: M.spmv(x, y), n, 3)
-        return _avg_us(ms)
+        return time_region(lambda: M.spmv(x, y), n, 3)[1] * 1e3
 
     table = {}
     for name in ("laplacian2d_2048", "fem3d_48x3"):
@@ -529,15 +541,23 @@ def main():
     flops = 2.0 * A.nnz
 
     def measure(M, steps, warmup, nbytes, flush=None):
+        """Mean launch time from one event pair around `steps` back-to-back
+        launches; with a cache flush between launches, from an event pair
+        around every launch (the flush stays outside the events)."""
         y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
-        wall, ms = time_launches(lambda: M.spmv(x, y), steps, warmup, flush)
+        if flush is None:
+            wall, avg = time_region(lambda: M.spmv(x, y), steps, warmup)
+            # per-launch event pairs on a few more launches: the fastest launch
+            _, ms = time_launches(lambda: M.spmv(x, y), min(steps, 20), 0)
+        else:
+            wall, ms = time_launches(lambda: M.spmv(x, y), steps, warmup, flush)
+            avg = float(np.mean(ms))
         err = oracle.rel_l2(y.cpu().numpy(), yref)
-        avg = float(np.mean(ms))
         return {"gflops": round(flops / (avg * 1e-3) / 1e9, 2),
                 "launch_us": round(avg * 1e3, 2), "min_launch_us": round(min(ms) * 1e3, 2),
                 "gbs": round(nbytes / (avg * 1e-3) / 1e9, 1),
                 "frac_hbm": round(nbytes / (avg * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
-                "bytes": int(nbytes), "rel_l2": err}, wall, ms
+                "bytes": int(nbytes), "rel_l2": err}, wall, avg
 
     if args.calibration_copy:
         src = torch.ones(COPY_ELEMS, dtype=torch.float64, device=dev)
@@ -550,10 +570,10 @@ def main():
     M = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, *rc)
     nbytes = M.info.spmv_bytes
     log(f"timing {args.steps} steps after {args.warmup} warmup")
-    prim, wall, ms = measure(M, args.steps, args.warmup, nbytes)
+    prim, wall, avg_ms = measure(M, args.steps, args.warmup, nbytes)
     if not prim["rel_l2"] <= 1e-14:
         raise SystemExit(f"parity failure: rel L2 {prim['rel_l2']}")
-    avg_s = float(np.mean(ms)) * 1e-3
+    avg_s = avg_ms * 1e-3
     achieved = nbytes / avg_s / 1e9
     out = {
         "metric": METRIC,
@@ -613,8 +633,7 @@ def main():
         M3 = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, *rc, "float32")
         x32 = x.float()
         y32 = torch.empty(A.nrows, dtype=torch.float32, device=dev)
-        _, ms32 = time_launches(lambda: M3.spmv(x32, y32), 50, 5)
-        us32 = _avg_us(ms32)
+        us32 = time_region(lambda: M3.spmv(x32, y32), 50, 5)[1] * 1e3
         formats[f"float32 beta({rc[0]},{rc[1]})"] = {
             "gflops": round(flops / us32 / 1e3, 2), "launch_us": round(us32, 2),
             "gbs": round(M3.info.spmv_bytes / us32 / 1e3, 1),

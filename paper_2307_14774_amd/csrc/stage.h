@@ -109,6 +109,38 @@ __device__ __forceinline__ void lds_block_masks(const uint8_t *sm, int t, int i,
     }
 }
 
+// Union of the r row masks of block t and the block's value count, from one
+// LDS read where the r masks fill 1, 2, 4 or 8 bytes.
+template <int R, int C>
+__device__ __forceinline__ void lds_block_union_count(const uint8_t *sm, int t, unsigned &u,
+                                                      int &tot) {
+    using MT = typename MaskOf<C>::type;
+    constexpr int MB = (int)sizeof(MT);
+    constexpr int WB = R * MB;
+    u = 0;
+    if constexpr (WB == 1 || WB == 2 || WB == 4 || WB == 8) {
+        uint64_t w;
+        if constexpr (WB == 1) w = sm[t];
+        else if constexpr (WB == 2) w = *(const uint16_t *)(sm + 2 * t);
+        else if constexpr (WB == 4) w = *(const uint32_t *)(sm + 4 * t);
+        else w = *(const uint64_t *)(sm + 8 * t);
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+            u |= (unsigned)(w >> (rr * 8 * MB)) & ((1u << (8 * MB)) - 1u);
+        tot = __popcll(w);
+    } else {
+        tot = 0;
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            unsigned mr;
+            if constexpr (MB == 1) mr = sm[t * R + rr];
+            else mr = ((const uint16_t *)sm)[t * R + rr];
+            u |= mr;
+            tot += __popc(mr);
+        }
+    }
+}
+
 // Union of the r row masks of block t (the columns the block touches).
 template <int R, int C>
 __device__ __forceinline__ unsigned lds_block_union(const uint8_t *sm, int t) {

@@ -66,9 +66,13 @@ __device__ __forceinline__ T tile_rows(int np, int b0, int b1, const int *sbp, c
     const int lps = S * R;
     const int pl = th / lps, sub = (th / R) & (S - 1), i = th % R;
     const bool live = pl < np;
-    // a piece tile holds only part of its panel's blocks: clamp
-    const int bs = live ? max(sbp[pl], b0) - b0 : 0;
-    const int be = live ? min(sbp[pl + 1], b1) - b0 : 0;
+    // a piece tile holds only part of its panel's blocks: clamp.  Both
+    // bounds are read on every thread (panel 0's on threads without a panel),
+    // so the two reads go out together.
+    const int plc = live ? pl : 0;
+    const int sb0 = sbp[plc], sb1 = sbp[plc + 1];
+    const int bs = live ? max(sb0, b0) - b0 : 0;
+    const int be = live ? min(sb1, b1) - b0 : 0;
     // Masked-off (block, bit) pairs read a zero from s_zero for both
     // operands, so the FMA needs no select: 0*0 leaves the sum unchanged
     // and a non-finite x of another row's column is never touched.
@@ -88,8 +92,10 @@ __device__ __forceinline__ T tile_rows(int np, int b0, int b1, const int *sbp, c
             j[u] = s_boff[tt[u]] + pre;
         }
         if constexpr (SPARSE) {
-            // low fill: one step per set bit, the wave running as many
-            // steps as its fullest row-block has bits
+            // low fill: the set bits two at a time (both pairs of LDS reads
+            // in flight together), the wave running as many steps as its
+            // fullest row-block has bit pairs; the products are added in
+            // ascending bit order
             T a = acc[0];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -97,12 +103,17 @@ __device__ __forceinline__ T tile_rows(int np, int b0, int b1, const int *sbp, c
                 int jj = j[u];
                 const T *xb = s_x + tt[u] * C;
                 while (__ballot(mm != 0u)) {
-                    const bool on = mm != 0u;
-                    const T *pv = on ? sval + jj : s_zero;
-                    const T *px = on ? xb + (__ffs(mm) - 1) : s_zero;
-                    a = fma(*pv, *px, a);
-                    ++jj;
-                    mm &= mm - 1u;
+                    const unsigned m1 = mm & (mm - 1u);
+                    const bool on0 = mm != 0u, on1 = m1 != 0u;
+                    const T *pv0 = on0 ? sval + jj : s_zero;
+                    const T *px0 = on0 ? xb + (__ffs(mm) - 1) : s_zero;
+                    const T *pv1 = on1 ? sval + jj + 1 : s_zero;
+                    const T *px1 = on1 ? xb + (__ffs(m1) - 1) : s_zero;
+                    const T v0 = *pv0, x0 = *px0, v1 = *pv1, x1 = *px1;
+                    a = fma(v0, x0, a);
+                    a = fma(v1, x1, a);
+                    jj += 2;
+                    mm = m1 & (m1 - 1u);
                 }
             }
             acc[0] = a;
@@ -218,11 +229,18 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
         const int np = p1 - p0;
         const int nbt = b1 - b0;
 
-        // 3. single x load per block (thread per block) ...
+        // 3. single x load per block (thread per block) ...  The block's
+        // masks and anchor are read whether or not the thread has a block
+        // (index 0 then, inside the buffers; the results are dropped), so the
+        // reads go out together instead of one behind the other.
         const bool has = th < nbt;
         const int tb = has ? th : 0;
-        const unsigned un = has ? lds_block_union<R, C>(smb, tb) : 0u;
-        const int col0 = has ? scol[tb] : 0;
+        unsigned un;
+        int cnt;
+        lds_block_union_count<R, C>(smb, tb, un, cnt);
+        un = has ? un : 0u;
+        cnt = has ? cnt : 0;
+        const int col0 = scol[tb];
         // The whole window x[anchor .. anchor+C) in 16-byte loads: the buffer
         // range check is per dword, so a window running past the last column
         // reads zeros there, and blocks whose rows use no column read nothing.
@@ -244,12 +262,6 @@ __global__ __launch_bounds__(kWG) void k_spmv_stream(
         __builtin_amdgcn_sched_barrier(0);
 
         // 2. block value offsets (workgroup exclusive scan of block popcounts)
-        int cnt = 0;
-        if (has) {
-            unsigned mm;
-            int pp;
-            lds_block_masks<R, C>(smb, tb, 0, mm, pp, cnt);
-        }
         const int incl = wave_incl_scan(cnt);
         if (lane == kWave - 1) s_wsum[wv] = incl;
         if (has) {

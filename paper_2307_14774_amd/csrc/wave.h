@@ -12,14 +12,23 @@ constexpr int kXcds = 8;   // MI355X: 8 accelerator complex dies, one L2 each
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
-// Inclusive prefix sum of an int over the 64 lanes of the wavefront.
+// Inclusive prefix sum of an int over the 64 lanes of the wavefront, built
+// from DPP lane moves so that it costs VALU operations only (a shuffle-based
+// scan waits on six LDS-unit round trips in a row).  Steps: shifts by 1, 2,
+// 4 and 8 lanes inside each 16-lane row (lanes shifted in from outside the
+// row read 0) give every row its own inclusive scan; then the last lane of
+// row 0 is added into row 1 and the last lane of row 2 into row 3 (row
+// broadcast of lane 15 with rows 1 and 3 enabled), and the last lane of row
+// 1 -- by then the total of rows 0-1 -- into rows 2 and 3 (broadcast of lane
+// 31 with rows 2 and 3 enabled).  Every lane of the wavefront must be active.
 __device__ __forceinline__ int wave_incl_scan(int v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int t = __shfl_up(v, d);
-        if (lane >= d) v += t;
-    }
+    constexpr int kRowShr = 0x110, kBcast15 = 0x142, kBcast31 = 0x143;
+    v += __builtin_amdgcn_update_dpp(0, v, kRowShr + 1, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kRowShr + 2, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kRowShr + 4, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kRowShr + 8, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kBcast15, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kBcast31, 0xc, 0xf, false);
     return v;
 }
 
