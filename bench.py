@@ -503,7 +503,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="laplacian")
     ap.add_argument("--no-extras", action="store_true", help="only the primary format")
     ap.add_argument("--no-cpu-baseline", action="store_true")
