@@ -166,8 +166,26 @@ __device__ __forceinline__ T tile_rows(int np, int b0, int b1, const int *sbp, c
     return accs;
 }
 
+// Workgroups of k_spmv_stream that the LDS of a compute unit (160 KiB, in
+// 512-byte allocation units) holds at once, at most 8.  The kernel asks the
+// compiler for that many wavefronts per SIMD, so that registers do not cap
+// residency below what LDS allows.
+template <typename T, int R, int C, int NVG, int VAR>
+constexpr int stream_residency() {
+    using Cfg = StreamCfg<T, R, C, NVG>;
+    constexpr int lds = 16 * (Cfg::VVEC + Cfg::MVEC + Cfg::CVEC + Cfg::PVEC) +
+                        Cfg::BT * C * (int)sizeof(T) + 4 * Cfg::BT + 4 * (kWG / kWave) +
+                        (int)sizeof(T) * ((VAR & kVarRowReduce) ? kWG + 1 : 2);
+    constexpr int units = (lds + 511) / 512;
+    constexpr int wg = (160 * 1024 / 512) / units;
+    // FP32 with value buffers of at most 8 KiB only: elsewhere the register
+    // budget this implies makes the compiler spill
+    return sizeof(T) == 4 && NVG <= 2 && R != 3 ? (wg > 8 ? 8 : wg) : 1;
+}
+
 template <typename T, int R, int C, int NVG, bool SPARSE, int VAR>
-__global__ __launch_bounds__(kWG) void k_spmv_stream(
+__global__ __launch_bounds__(kWG)
+__attribute__((amdgpu_waves_per_eu(stream_residency<T, R, C, NVG, VAR>()))) void k_spmv_stream(
     int64_t nrows, int64_t ncols, int64_t ntiles, int tiles_per_wg, int64_t nwg, int remap,
     const int32_t *__restrict__ tile_p, const int32_t *__restrict__ tile_b,
     const int32_t *__restrict__ tile_v, const int32_t *__restrict__ tile_f,
