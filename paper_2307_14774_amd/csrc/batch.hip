@@ -129,12 +129,13 @@ template <typename T>
 struct VTileLds {
     using Cfg = StreamCfg<T, 1, 16, kBatchNVG<T>>;
     static constexpr int VCAP = Cfg::VVEC * 16 / (int)sizeof(T);
+    static_assert(VCAP < 65536, "block value offsets kept in 16 bits");
     v4u val[Cfg::VVEC];
     v4u mask[Cfg::MVEC];
     v4u col[Cfg::CVEC];
     v4u bp[Cfg::PVEC];
     int vcol[VCAP];
-    int boff[Cfg::BT + 1];
+    uint16_t boff[Cfg::BT + 2];    // first value of every block (< VCAP)
     int wsum[kWG / kWave];
     int longrow[kWG];
     int nlong;
@@ -226,8 +227,11 @@ __device__ __forceinline__ TileBounds item_bounds(const BatchDescV &d, int64_t t
 // KC-wide x loads.  A butterfly over the S sub-lanes of a row, one store.
 constexpr int kGrab = 4;
 
+// FP32 tiles leave LDS for 6 resident workgroups per compute unit; the
+// register budget is set to match.
 template <typename T, int KC>
-__global__ __launch_bounds__(kWG) void k_batch_v(const BatchDescV *__restrict__ descs,
+__global__ __launch_bounds__(kWG)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1))) void k_batch_v(const BatchDescV *__restrict__ descs,
                                                  const int32_t *__restrict__ work, int64_t nwork,
                                                  unsigned *counter, int nch, int ld,
                                                  T *__restrict__ partial) {
@@ -297,12 +301,12 @@ __global__ __launch_bounds__(kWG) void k_batch_v(const BatchDescV *__restrict__ 
                 total += L.wsum[w2];
             }
             int boff = before + incl - own;
-            if (th == 0) L.boff[nbt] = total;
+            if (th == 0) L.boff[nbt] = (uint16_t)total;
 #pragma unroll
             for (int q = 0; q < BPT; ++q) {
                 const int tb = BPT * th + q;
                 if (tb < nbt) {
-                    L.boff[tb] = boff;
+                    L.boff[tb] = (uint16_t)boff;
                     const int c0b = scol[tb];
                     unsigned mm = m[q];
                     int v = boff;

@@ -322,8 +322,23 @@ __attribute__((amdgpu_waves_per_eu(stream_residency<T, R, C, NVG, VAR>()))) void
 // rows -- contiguous value ranges for r = 1 -- are summed by S sub-lanes and
 // a butterfly.  The staging, prefetch and piece tiles are those of the
 // staged kernel.
+// Workgroups of k_spmv_vstream that the LDS of a compute unit holds at once
+// (as for k_spmv_stream), requested from the compiler for FP32 only and at
+// most 6: beyond that the register budget makes it spill.
 template <typename T, int C, int NVG>
-__global__ __launch_bounds__(kWG) void k_spmv_vstream(
+constexpr int vstream_residency() {
+    using Cfg = StreamCfg<T, 1, C, NVG>;
+    constexpr int vcap = Cfg::VVEC * 16 / (int)sizeof(T);
+    constexpr int lds = 16 * (Cfg::VVEC + Cfg::MVEC + Cfg::CVEC + Cfg::PVEC) + 4 * vcap +
+                        2 * (Cfg::BT + 2) + 4 * (kWG / kWave) + 4 * kWG + 4;
+    constexpr int units = (lds + 511) / 512;
+    constexpr int wg = (160 * 1024 / 512) / units;
+    return sizeof(T) == 4 ? (wg > 6 ? 6 : wg) : 1;
+}
+
+template <typename T, int C, int NVG>
+__global__ __launch_bounds__(kWG)
+__attribute__((amdgpu_waves_per_eu(vstream_residency<T, C, NVG>()))) void k_spmv_vstream(
     int64_t nrows, int64_t ncols, int64_t ntiles, int tiles_per_wg, int64_t nwg, int remap,
     const int32_t *__restrict__ tile_p, const int32_t *__restrict__ tile_b,
     const int32_t *__restrict__ tile_v, const int32_t *__restrict__ tile_f,
@@ -342,7 +357,9 @@ __global__ __launch_bounds__(kWG) void k_spmv_vstream(
     __shared__ v4u s_col[Cfg::CVEC];
     __shared__ v4u s_bp[Cfg::PVEC];
     __shared__ int s_vcol[VCAP];
-    __shared__ int s_boff[BT + 1];
+    // first value of every block inside the tile (< VCAP, so 16 bits do)
+    __shared__ uint16_t s_boff[BT + 2];
+    static_assert(VCAP < 65536, "block value offsets kept in 16 bits");
     __shared__ int s_wsum[kWG / kWave];
     __shared__ int s_long[kWG];
     __shared__ int s_nlong;
@@ -408,13 +425,13 @@ __global__ __launch_bounds__(kWG) void k_spmv_vstream(
             total += s_wsum[w2];
         }
         int boff = before + incl - own;
-        if (th == 0) s_boff[nbt] = total;
+        if (th == 0) s_boff[nbt] = (uint16_t)total;
         // column of every value: anchor + position of each set bit
 #pragma unroll
         for (int q = 0; q < BPT; ++q) {
             const int tb = BPT * th + q;
             if (tb < nbt) {
-                s_boff[tb] = boff;
+                s_boff[tb] = (uint16_t)boff;
                 const int c0b = scol[tb];
                 unsigned mm = m[q];
                 int v = boff;
