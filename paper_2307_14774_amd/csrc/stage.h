@@ -37,8 +37,9 @@ struct StreamCfg {
 
 // Values per value-mode (beta(1,c)) tile for an element of sz bytes, 16 bytes
 // of padding included: 8 KiB of LDS in FP32, 12 KiB in FP64.  Each value also
-// keeps its decoded column in LDS; these sizes leave room for 5-6 resident
-// workgroups per compute unit, which the per-nonzero gathers need.
+// keeps its decoded column in LDS; with block offsets in 16 bits these sizes
+// leave room for 6 resident workgroups per compute unit in FP32 and 5 in
+// FP64, which the per-nonzero gathers need.
 constexpr int value_tile(int sz) { return sz == 8 ? 1536 : 2048; }
 
 // Tile capacities for a matrix (must match StreamCfg).
