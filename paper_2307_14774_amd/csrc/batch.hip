@@ -230,11 +230,9 @@ constexpr int kGrab = 4;
 // FP32 tiles leave LDS for 6 resident workgroups per compute unit; the
 // register budget is set to match.
 template <typename T, int KC>
-__global__ __launch_bounds__(kWG)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1))) void k_batch_v(const BatchDescV *__restrict__ descs,
-                                                 const int32_t *__restrict__ work, int64_t nwork,
-                                                 unsigned *counter, int nch, int ld,
-                                                 T *__restrict__ partial) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1)))
+void k_batch_v(const BatchDescV *__restrict__ descs, const int32_t *__restrict__ work,
+               int64_t nwork, unsigned *counter, int nch, int ld, T *__restrict__ partial) {
     __shared__ VTileLds<T> L;
     __shared__ unsigned s_w;
     constexpr int VCAP = VTileLds<T>::VCAP;

@@ -110,8 +110,9 @@ __device__ __forceinline__ void lds_block_masks(const uint8_t *sm, int t, int i,
     }
 }
 
-// Union of the r row masks of block t and the block's value count, from one
-// LDS read where the r masks fill 1, 2, 4 or 8 bytes.
+// Union of the r row masks of block t (the columns the block touches) and
+// the block's value count, from one LDS read where the r masks fill 1, 2, 4
+// or 8 bytes.
 template <int R, int C>
 __device__ __forceinline__ void lds_block_union_count(const uint8_t *sm, int t, unsigned &u,
                                                       int &tot) {
@@ -140,20 +141,6 @@ __device__ __forceinline__ void lds_block_union_count(const uint8_t *sm, int t, 
             tot += __popc(mr);
         }
     }
-}
-
-// Union of the r row masks of block t (the columns the block touches).
-template <int R, int C>
-__device__ __forceinline__ unsigned lds_block_union(const uint8_t *sm, int t) {
-    using MT = typename MaskOf<C>::type;
-    constexpr int MB = (int)sizeof(MT);
-    unsigned u = 0;
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) {
-        if constexpr (MB == 1) u |= sm[t * R + rr];
-        else u |= ((const uint16_t *)sm)[t * R + rr];
-    }
-    return u;
 }
 
 // A contiguous byte range of global memory, as 16-byte vectors from an

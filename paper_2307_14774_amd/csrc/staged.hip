@@ -312,16 +312,6 @@ __attribute__((amdgpu_waves_per_eu(stream_residency<T, R, C, NVG, VAR>()))) void
 
 // ---------------------------------------------------------------- value mode
 
-// beta(1,c) in VALUE MODE: with one row per block there is no x window to
-// share between rows, and at low fill most of a block's c columns are empty,
-// so the x loads go per nonzero instead of per block column.  Per tile: the
-// block popcount scan gives every block its first value; one thread per block
-// decodes its values' columns (anchor + position of each set bit) into LDS;
-// every thread then gathers x for a fixed number of value slots (unconditional
-// buffer loads, out of range past the tile), multiplies in place, and the
-// rows -- contiguous value ranges for r = 1 -- are summed by S sub-lanes and
-// a butterfly.  The staging, prefetch and piece tiles are those of the
-// staged kernel.
 // Workgroups of k_spmv_vstream that the LDS of a compute unit holds at once
 // (as for k_spmv_stream), requested from the compiler for FP32 only and at
 // most 6: beyond that the register budget makes it spill.
@@ -336,6 +326,16 @@ constexpr int vstream_residency() {
     return sizeof(T) == 4 ? (wg > 6 ? 6 : wg) : 1;
 }
 
+// beta(1,c) in VALUE MODE: with one row per block there is no x window to
+// share between rows, and at low fill most of a block's c columns are empty,
+// so the x loads go per nonzero instead of per block column.  Per tile: the
+// block popcount scan gives every block its first value; one thread per block
+// decodes its values' columns (anchor + position of each set bit) into LDS;
+// every thread then gathers x for a fixed number of value slots (unconditional
+// buffer loads, out of range past the tile), multiplies in place, and the
+// rows -- contiguous value ranges for r = 1 -- are summed by S sub-lanes and
+// a butterfly.  The staging, prefetch and piece tiles are those of the
+// staged kernel.
 template <typename T, int C, int NVG>
 __global__ __launch_bounds__(kWG)
 __attribute__((amdgpu_waves_per_eu(vstream_residency<T, C, NVG>()))) void k_spmv_vstream(
