@@ -10,7 +10,7 @@
 namespace spc5 {
 
 constexpr int kWG = 256;   // threads per workgroup (4 wavefronts)
-constexpr int kXcdRun = 16; // consecutive workgroups kept on one XCD (xcd_chunks)
+constexpr int kXcdRun = 32; // consecutive workgroups kept on one XCD (xcd_chunks)
 
 template <typename T, int R, int C, int NVG = 4>
 struct StreamCfg {
