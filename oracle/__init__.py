@@ -3,18 +3,22 @@
 Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package.  The product path never calls it and shares no code with it.
 
-The arithmetic lives in ``spc5_oracle.c`` (built with ``-ffp-contract=off`` so
-every product is rounded before it is added).  This module only marshals numpy
+The arithmetic lives in ``spc5_oracle.c`` (built with ``-O3 -ffp-contract=off``
+so every product is rounded before it is added, and with OpenMP for the
+threaded host-baseline form of O1).  This module only marshals numpy
 arrays to it, plus a few dense helpers used on tiny cases.
 
 Functions and the passage of arXiv 2307.14774 each one follows:
 
 * ``csr_spmv``          -- O1, y = A x by the CSR definition (Section 2.3).
+* ``csr_spmv_par``      -- O1 with its rows split over CPU threads (host
+                           baseline only; bitwise equal to ``csr_spmv``).
 * ``csr_spmm``          -- O1 over several right-hand sides.
 * ``csr_spmv_t``        -- O2, xbar = A^T ybar by definition.
 * ``csr_to_spc5``       -- O3, greedy beta(r,c) blocking (Section 2.4).
 * ``spc5_to_csr``       -- O4, inverse expansion (Fig. 2 caption).
-* ``spc5_spmv``         -- O5, scalar variant of Algorithm 1.
+* ``spc5_spmv``         -- O5, the beta(r,c) product by the format's
+                           definition: O4 to CSR, then O1 (Section 2.4).
 * ``spc5_values_grad``  -- O6, d<ybar, A(theta) x>/d theta in packed order.
 """
 from __future__ import annotations
@@ -34,11 +38,12 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc (no FMA contraction, no fast-math)."""
+    """Compile the C oracle with gcc (no FMA contraction, no fast-math;
+    OpenMP only spreads whole rows of the host-baseline O1 over threads)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+            ["gcc", "-O3", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
              "-fPIC", "-shared", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
@@ -53,6 +58,7 @@ def _load():
         I64 = ctypes.c_int64
         I = ctypes.c_int
         lib.oracle_csr_spmv.argtypes = [I64, P, P, P, P, P]
+        lib.oracle_csr_spmv_par.argtypes = [I64, P, P, P, P, P, I]
         lib.oracle_csr_spmm.argtypes = [I64, P, P, P, I64, P, P]
         lib.oracle_csr_spmv_t.argtypes = [I64, I64, P, P, P, P, P]
         lib.oracle_spc5_count.argtypes = [I64, P, P, I, I, P]
@@ -61,7 +67,7 @@ def _load():
         lib.oracle_spc5_to_csr.argtypes = [I64, I, I, P, P, P, P, P, P, P]
         lib.oracle_spc5_spmv.argtypes = [I64, I, I, P, P, P, P, P, P]
         lib.oracle_spc5_values_grad.argtypes = [I64, I, I, P, P, P, P, P, P]
-        for f in ("oracle_csr_spmv", "oracle_csr_spmm", "oracle_csr_spmv_t",
+        for f in ("oracle_csr_spmv", "oracle_csr_spmv_par", "oracle_csr_spmm", "oracle_csr_spmv_t",
                   "oracle_csr_to_spc5", "oracle_spc5_to_csr", "oracle_spc5_spmv",
                   "oracle_spc5_values_grad"):
             getattr(lib, f).restype = None
@@ -111,6 +117,18 @@ def csr_spmv(rowptr, colidx, values, x) -> np.ndarray:
     nrows = rowptr.shape[0] - 1
     y = np.empty(nrows, dtype=np.float64)
     _load().oracle_csr_spmv(nrows, _p(rowptr), _p(colidx), _p(values), _p(x), _p(y))
+    return y
+
+
+def csr_spmv_par(rowptr, colidx, values, x, nthreads: int) -> np.ndarray:
+    """O1 with the rows cut into `nthreads` equal contiguous ranges, one per
+    thread (host baseline only)."""
+    rowptr, colidx, values = _csr_arrays(rowptr, colidx, values)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    nrows = rowptr.shape[0] - 1
+    y = np.empty(nrows, dtype=np.float64)
+    _load().oracle_csr_spmv_par(nrows, _p(rowptr), _p(colidx), _p(values), _p(x), _p(y),
+                                int(nthreads))
     return y
 
 

@@ -7,8 +7,10 @@
  * HIP library) never calls it, shares no code with it, and must fail loudly
  * rather than fall back to it.
  *
- * Everything is FP64 and strictly sequential.  Build with -ffp-contract=off so
- * that no multiply-add is fused: each product is rounded, then added.
+ * Everything is FP64.  Every sum is strictly sequential; only the
+ * host-baseline form of O1 spreads whole rows over threads.  Build with
+ * -ffp-contract=off so that no multiply-add is fused: each product is
+ * rounded, then added.
  *
  * Paper: Regnault & Bramas, "SPC5: an efficient SpMV framework vectorized
  * using ARM SVE and x86 AVX-512" (arXiv 2307.14774).
@@ -37,6 +39,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* O1. Plain CSR SpMV, the definition y_i = sum_j A_ij x_j (Section 2.3, CSR;
  * the paper's scalar "CSR" baseline).  Each row sums from +0.0 in ascending
@@ -51,6 +56,34 @@ void oracle_csr_spmv(int64_t nrows, const int64_t *rowptr, const int32_t *colidx
             s = s + p;
         }
         y[i] = s;
+    }
+}
+
+/* O1 on several CPU threads, for the host baseline only: the rows are cut
+ * into nthreads contiguous ranges of equal row count, one per thread (the
+ * paper's parallel runs split the rows "naively" among the threads, Section
+ * 4.3).  Every row is still summed by one thread from +0.0 in ascending
+ * storage order, so y is bitwise equal to O1. */
+void oracle_csr_spmv_par(int64_t nrows, const int64_t *rowptr, const int32_t *colidx,
+                         const double *values, const double *x, double *y, int nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+    {
+        int t = 0, nt = 1;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+        nt = omp_get_num_threads();
+#endif
+        int64_t lo = nrows * t / nt, hi = nrows * (t + 1) / nt;
+        for (int64_t i = lo; i < hi; ++i) {
+            double s = 0.0;
+            for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                double q = values[k] * x[colidx[k]];
+                s = s + q;
+            }
+            y[i] = s;
+        }
     }
 }
 
@@ -199,34 +232,29 @@ void oracle_spc5_to_csr(int64_t nrows, int r, int c, const int64_t *blk_ptr,
     free(fill);
 }
 
-/* O5. Scalar SPC5 SpMV, the scalar variant of Algorithm 1: walk panels, their
- * blocks, the rows of each block and the mask bits in ascending order, with a
- * running index into the packed values; one partial sum per panel row.
- * y is overwritten (rows past nrows in the last panel are skipped). */
+/* O5. The SPC5 product read straight from the format's definition
+ * (Section 2.4, Fig. 2 caption): the beta(r,c) arrays describe the matrix
+ * whose row p*r+i holds, for every block b of panel p and every set bit k of
+ * the mask of row i, the entry (anchor(b)+k, next packed value).  So the
+ * product is O4 (decode to CSR) followed by O1 (the CSR definition).  Each
+ * row is still summed from +0.0 in ascending column order, which makes the
+ * result bitwise equal to O1 on the original CSR.  y is overwritten. */
 void oracle_spc5_spmv(int64_t nrows, int r, int c, const int64_t *blk_ptr,
                       const int32_t *blk_col, const uint16_t *masks,
                       const double *packed, const double *x, double *y)
 {
-    int64_t npanels = (nrows + r - 1) / r, v = 0;
-    double sum[8];
-    for (int64_t p = 0; p < npanels; ++p) {
-        for (int i = 0; i < r; ++i) sum[i] = 0.0;
-        for (int64_t b = blk_ptr[p]; b < blk_ptr[p + 1]; ++b) {
-            int64_t col = blk_col[b];
-            for (int i = 0; i < r; ++i) {
-                uint32_t m = masks[b * r + i];
-                for (int k = 0; k < c; ++k) {
-                    if ((m >> k) & 1u) {
-                        double prod = x[col + k] * packed[v];
-                        sum[i] = sum[i] + prod;
-                        v += 1;
-                    }
-                }
-            }
-        }
-        for (int i = 0; i < r; ++i)
-            if (p * r + i < nrows) y[p * r + i] = sum[i];
-    }
+    int64_t npanels = (nrows + r - 1) / r, nnz = 0;
+    for (int64_t q = 0; q < blk_ptr[npanels] * r; ++q)
+        for (int k = 0; k < c; ++k)
+            if ((masks[q] >> k) & 1u) nnz += 1;
+    int64_t *rowptr = (int64_t *)malloc((size_t)(nrows + 1) * sizeof(int64_t));
+    int32_t *colidx = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
+    double *values = (double *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
+    oracle_spc5_to_csr(nrows, r, c, blk_ptr, blk_col, masks, packed, rowptr, colidx, values);
+    oracle_csr_spmv(nrows, rowptr, colidx, values, x, y);
+    free(values);
+    free(colidx);
+    free(rowptr);
 }
 
 /* O6. Gradient of L = <ybar, A(theta) x> with respect to the packed values:

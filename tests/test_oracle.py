@@ -272,6 +272,23 @@ def test_fem_closed_forms(n):
     np.testing.assert_allclose(d, off + 1.0, rtol=1e-12)
 
 
+@pytest.mark.parametrize("n", [6, 8, 10, 16])
+def test_fem_closed_forms_multirow(n):
+    """beta(r,c) block counts of the FEM matrix against the panel-cover closed
+    form (tests/helpers.py), every shape whose r divides 3n; at n = 96 the
+    form gives 46,623,720 (beta(1,8)), 35,172,280 (beta(2,4)) and 17,667,936
+    (beta(4,4))."""
+    from helpers import fem_block_count
+    A = W.fem_3d(n, seed=1)
+    for r, c in [(1, 8), (2, 4), (4, 4), (1, 16), (2, 8), (4, 8), (8, 8), (3, 5), (6, 16)]:
+        if (3 * n) % r:
+            continue
+        assert oracle.spc5_count(A.rowptr, A.colidx, r, c) == fem_block_count(n, r, c), (r, c)
+    assert fem_block_count(96, 1, 8) == 46_623_720
+    assert fem_block_count(96, 2, 4) == 35_172_280
+    assert fem_block_count(96, 4, 4) == 17_667_936
+
+
 def test_fig3_expand_golden():
     g = json.load(open(os.path.join(GOLDEN, "fig3_expand.json")))
     S = oracle.csr_to_spc5(np.array(g["rowptr"]), np.array(g["colidx"], np.int32),
@@ -296,11 +313,27 @@ def test_table1_dense_fill(prec):
         assert round(100 * A.nnz / (nb * r * c)) == pct
 
 
-# ---------------------------------------------------------------- O5: Algorithm 1
+@pytest.mark.parametrize("A", edge_cases() + [W.laplacian_2d(33, seed=4),
+                                               W.random_sparse(1001, 700, 0.02, seed=5)],
+                         ids=lambda a: a.name)
+@pytest.mark.parametrize("nthreads", [1, 2, 3, 8])
+def test_csr_spmv_par_bitwise(A, nthreads):
+    """The threaded host-baseline O1 gives every row to one thread, which sums
+    it in storage order: bitwise equal to the sequential O1, and equal to
+    scipy's product within rounding."""
+    y1 = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
+    yp = oracle.csr_spmv_par(A.rowptr, A.colidx, A.values, A.x, nthreads)
+    assert np.array_equal(yp.view(np.uint64), y1.view(np.uint64))
+    if A.nrows and A.ncols:
+        S = sp.csr_matrix((A.values, A.colidx, A.rowptr), shape=(A.nrows, A.ncols))
+        np.testing.assert_allclose(yp, S @ A.x, rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------- O5: the beta(r,c) product
 
 @pytest.mark.parametrize("A", edge_cases(), ids=lambda a: a.name)
 @pytest.mark.parametrize("rc", SHAPES[:8], ids=lambda t: "b%d_%d" % t)
-def test_alg1_equals_csr_definition_bitwise(A, rc):
+def test_spc5_product_equals_csr_definition_bitwise(A, rc):
     r, c = rc
     S = oracle.csr_to_spc5(A.rowptr, A.colidx, A.values, A.ncols, r, c)
     y5 = oracle.spc5_spmv(S, A.x)
@@ -308,7 +341,7 @@ def test_alg1_equals_csr_definition_bitwise(A, rc):
     assert np.array_equal(y5.view(np.uint64), y1.view(np.uint64))
 
 
-def test_alg1_laplacian_vs_scipy():
+def test_spc5_product_laplacian_vs_scipy():
     A = W.laplacian_2d(40, seed=2)
     Sm = sp.csr_matrix((A.values, A.colidx, A.rowptr), shape=(A.nrows, A.ncols))
     for r, c in [(1, 8), (2, 4), (4, 4)]:

@@ -34,9 +34,14 @@ MUTANTS = {
                       "(anchor < 0 || colidx[cur[i]] > anchor)"),
     "o4_col_offset": ("colidx[fill[row]] = blk_col[b] + k;",
                       "colidx[fill[row]] = blk_col[b] + k + (k > 0);"),
-    "o5_row_index": ("sum[i] = sum[i] + prod;", "sum[0] = sum[0] + prod;"),
-    "o5_value_index": ("double prod = x[col + k] * packed[v];",
-                       "double prod = x[col + k] * packed[v > 0 ? v - 1 : 0];"),
+    "o5_packed_order": ("oracle_csr_spmv(nrows, rowptr, colidx, values, x, y);",
+                        "oracle_csr_spmv(nrows, rowptr, colidx, packed, x, y);"),
+    "o5_top_bit": ("oracle_spc5_to_csr(nrows, r, c, blk_ptr",
+                   "oracle_spc5_to_csr(nrows, r, c > 1 ? c - 1 : c, blk_ptr"),
+    "o1par_sign": ("double q = values[k] * x[colidx[k]];\n                s = s + q;",
+                   "double q = values[k] * x[colidx[k]];\n                s = s - q;"),
+    "o1par_split": ("hi = nrows * (t + 1) / nt;",
+                    "hi = nrows * (t + 1) / nt - (t + 1 < nt ? 1 : 0);"),
     "o6_row": ("vbar[v] = ybar[p * r + i] * x[blk_col[b] + k];",
                "vbar[v] = ybar[p * r] * x[blk_col[b] + k];"),
 }
@@ -46,6 +51,7 @@ def _pins():
     cases = T.edge_cases()
     A_tiny = T.tiny_cases()
     yield lambda: [T.test_csr_spmv_vs_dense_and_scipy(a) for a in A_tiny[10:20]]
+    yield lambda: [T.test_csr_spmv_par_bitwise(a, n) for a in cases[:12] for n in (2, 3)]
     yield lambda: T.test_csr_spmv_unit_vectors_give_columns()
     yield lambda: [T.test_transpose_vs_dense(a) for a in A_tiny[::3]]
     yield lambda: T.test_transpose_adjoint_and_unit_rows()
@@ -54,7 +60,7 @@ def _pins():
     yield lambda: [T.test_block_count_is_minimum_cover(rc, 0) for rc in [(1, 4), (4, 4)]]
     yield lambda: [T.test_laplacian_closed_forms(N) for N in (8, 16)]
     yield lambda: T.test_fig3_expand_golden()
-    yield lambda: [T.test_alg1_equals_csr_definition_bitwise(a, rc) for a in cases[:12]
+    yield lambda: [T.test_spc5_product_equals_csr_definition_bitwise(a, rc) for a in cases[:12]
                    for rc in [(1, 8), (2, 4), (4, 4)]]
     yield lambda: [T.test_values_grad_by_exact_central_difference(rc) for rc in [(2, 4)]]
 
@@ -67,8 +73,8 @@ def test_pins_catch_mutant(name, tmp_path, monkeypatch):
     mpath = tmp_path / "mutant.c"
     mpath.write_text(src.replace(old, new))
     lib = tmp_path / "libmutant.so"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC",
-                           "-shared", "-o", str(lib), str(mpath)])
+    subprocess.check_call(["gcc", "-O3", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                           "-fopenmp", "-fPIC", "-shared", "-o", str(lib), str(mpath)])
     monkeypatch.setattr(oracle, "_LIB", str(lib))
     monkeypatch.setattr(oracle, "_lib", None)
     monkeypatch.setattr(oracle, "build", lambda force=False: str(lib))
