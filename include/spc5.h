@@ -34,13 +34,15 @@
  *    synchronous.
  *  - A matrix handle is immutable after creation except for its schedule
  *    (spc5_set_schedule) and its transpose plan (spc5_prepare_transpose).
- *    Compute calls on one handle may overlap on several streams, with two
- *    exceptions that share a buffer held by the handle: forward products of
- *    a matrix whose staged schedule splits long panels
- *    (spc5_info.split_panels > 0: the pieces' partial sums), and transposes
- *    with caller values through a plan.  Those must be ordered (one stream
- *    or synchronised streams).  The caller must not free a handle while
- *    work that uses it is pending.
+ *    Compute calls on one handle may overlap on several streams.  Products
+ *    that need scratch memory (the partial row sums of panels cut into
+ *    pieces, spc5_info.split_panels > 0; the value move of a transpose with
+ *    caller values through a plan) take it from a set the handle keeps per
+ *    stream, allocated on the stream's first such call and held until
+ *    spc5_free: calls on one stream are ordered, and calls on different
+ *    streams never share scratch.  A HIP graph captured on a stream keeps
+ *    using that stream's set.  The caller must not free a handle while work
+ *    that uses it is pending.
  *  - Calls must be made with the HIP device that was current at creation.
  */
 #ifndef SPC5_H
@@ -212,10 +214,10 @@ int spc5_spmv_values(const spc5_matrix *A, const void *values, const void *x,
  * takes one atomic per workgroup rather than one per row.
  * With a plan (spc5_prepare_transpose): the forward kernel over the stored
  * A^T; no atomics, the result is reproducible bit for bit.  When `values` is
- * given, the plan first moves them to A^T's order (two passes through
- * buffers owned by A: a scatter into staging slots grouped by position in
- * A^T, then a gather inside each group), so such calls on one handle must
- * not overlap in time (one stream, or synchronised streams). */
+ * given, the plan first moves them to A^T's order (two passes through the
+ * calling stream's scratch, two value arrays of nnz entries: a scatter into
+ * staging slots grouped by position in A^T, then a gather inside each
+ * group). */
 int spc5_spmv_transpose(const spc5_matrix *A, const void *ybar, void *xbar,
                         void *stream);
 int spc5_spmv_transpose_values(const spc5_matrix *A, const void *values,
@@ -225,9 +227,9 @@ int spc5_spmv_transpose_values(const spc5_matrix *A, const void *values,
  * SPC5 beta(r,c) storage (r = c = 0: A's own shape) plus the two index
  * arrays that move caller values from A's packed order to A^T's.
  * Afterwards spc5_spmv_transpose* run as a forward product over A^T.  Costs
- * about the device memory of A once more, plus two more value arrays (the
- * staging and the moved values) and 8 bytes per nonzero (the two index
- * arrays); held until spc5_free.  Synchronous.
+ * about the device memory of A once more, plus 8 bytes per nonzero (the two
+ * index arrays); held until spc5_free.  Each stream that calls a transpose
+ * with caller values adds two value arrays of scratch.  Synchronous.
  * Calling it again with the same shape is a no-op.
  * Errors: SPC5_EINVAL (NULL A, a plan with another shape exists),
  * SPC5_EUNSUPPORTED (r or c out of range, A^T's block count >= 2^31),

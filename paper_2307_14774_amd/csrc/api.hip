@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <utility>
@@ -149,12 +150,77 @@ struct DeviceGuard {
     }
 };
 
+// One scratch set per stream that has called a product of the handle.  A
+// stream's set only grows (a part is allocated when a call first needs it),
+// and the handle frees them all.
+struct ScratchPool {
+    std::mutex mu;
+    struct Slot {
+        hipStream_t stream;
+        Scratch sc;
+    };
+    std::vector<Slot> slots;
+};
+
+void free_pool(spc5_matrix *A) {
+    if (!A->pool) return;
+    for (auto &sl : A->pool->slots)
+        for (void *p : {sl.sc.partial, sl.sc.tr_partial, sl.sc.stage, sl.sc.vals})
+            if (p) (void)hipFree(p);
+    delete A->pool;
+    A->pool = nullptr;
+}
+
+// hipMalloc that also works while the calling thread captures a graph (the
+// allocation itself is not a stream operation).
+static hipError_t scratch_alloc(void **p, size_t bytes) {
+    hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+    hipError_t e = hipThreadExchangeStreamCaptureMode(&mode);
+    if (e != hipSuccess) return e;
+    e = hipMalloc(p, bytes + kPad);
+    hipStreamCaptureMode back = mode;
+    const hipError_t e2 = hipThreadExchangeStreamCaptureMode(&back);
+    return e != hipSuccess ? e : e2;
+}
+
+int pool_scratch(const spc5_matrix *A, hipStream_t s, int need, Scratch *out) {
+    *out = Scratch();
+    const size_t vb = A->dtype == SPC5_F64 ? 8 : 4;
+    const spc5_matrix *T = A->tr;
+    size_t want[4] = {0, 0, 0, 0};    // partial, tr_partial, stage, vals
+    if ((need & kNeedPartial) && A->npieces > 0) want[0] = (size_t)A->npieces * A->r * vb;
+    if ((need & kNeedTrPartial) && T && T->npieces > 0)
+        want[1] = (size_t)T->npieces * T->r * vb;
+    if ((need & kNeedTheta) && A->nnz > 0) want[2] = want[3] = (size_t)A->nnz * vb;
+    if (!want[0] && !want[1] && !want[2]) return SPC5_OK;
+    if (!A->pool) return fail(SPC5_EINVAL, "handle has no scratch pool");
+    std::lock_guard<std::mutex> lock(A->pool->mu);
+    ScratchPool::Slot *slot = nullptr;
+    for (auto &sl : A->pool->slots)
+        if (sl.stream == s) slot = &sl;
+    if (!slot) {
+        A->pool->slots.push_back({s, Scratch()});
+        slot = &A->pool->slots.back();
+    }
+    void **part[4] = {&slot->sc.partial, &slot->sc.tr_partial, &slot->sc.stage, &slot->sc.vals};
+    for (int q = 0; q < 4; ++q) {
+        if (!want[q] || *part[q]) continue;
+        const hipError_t e = scratch_alloc(part[q], want[q]);
+        if (e != hipSuccess) {
+            *part[q] = nullptr;
+            return hip_fail(e, "allocating per-stream scratch");
+        }
+    }
+    *out = slot->sc;
+    return SPC5_OK;
+}
+
 void free_matrix(spc5_matrix *A) {
     if (!A) return;
     DeviceGuard g(A->device);
     free_matrix(A->tr);
-    for (void *p : {(void *)A->tr_lidx, (void *)A->tr_gpos, (void *)A->tr_src, A->tr_stage,
-                    A->tr_vals})
+    free_pool(A);
+    for (void *p : {(void *)A->tr_lidx, (void *)A->tr_gpos, (void *)A->tr_src})
         if (p) (void)hipFree(p);
     if (A->blk_ptr) (void)hipFree(A->blk_ptr);
     if (A->blk_col) (void)hipFree(A->blk_col);
@@ -193,8 +259,10 @@ int csr_to_spc5(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32
     if (!A) return fail(SPC5_ENOMEM, "host allocation failed");
     A->nrows = nrows; A->ncols = ncols; A->nnz = nnz; A->npanels = npanels;
     A->r = r; A->c = c; A->dtype = dtype; A->mask_bytes = c <= 8 ? 1 : 2;
+    A->pool = new (std::nothrow) ScratchPool();
+    if (!A->pool) { delete A; return fail(SPC5_ENOMEM, "host allocation failed"); }
     hipError_t e = hipGetDevice(&A->device);
-    if (e != hipSuccess) { delete A; return hip_fail(e, "hipGetDevice"); }
+    if (e != hipSuccess) { free_matrix(A); return hip_fail(e, "hipGetDevice"); }
     const int vb = dtype == SPC5_F64 ? 8 : 4;
     int64_t *d_rowptr = nullptr;
     int32_t *d_colidx = nullptr;
@@ -373,11 +441,21 @@ static int compute_guard(const spc5_matrix *A,
     return SPC5_OK;
 }
 
+// Partial-sum scratch of a forward product of A on stream s (none when A
+// has no piece tiles or another kernel than the staged one runs).
+static int forward_scratch(const spc5_matrix *A, hipStream_t s, Scratch *sc) {
+    *sc = Scratch();
+    if (A->kernel != SPC5_KERNEL_STAGED || A->npieces == 0) return SPC5_OK;
+    return pool_scratch(A, s, kNeedPartial, sc);
+}
+
 int spc5_spmv(const spc5_matrix *A, const void *x, void *y, void *stream) {
     int st = compute_guard(A, {{x, A ? A->ncols : 0}, {y, A ? A->nrows : 0}});
     if (st) return st;
     DeviceGuard g(A->device);
-    hipError_t e = launch_spmv(A, nullptr, x, y, (hipStream_t)stream);
+    Scratch sc;
+    if ((st = forward_scratch(A, (hipStream_t)stream, &sc)) != SPC5_OK) return st;
+    hipError_t e = launch_spmv(A, nullptr, x, y, (hipStream_t)stream, sc.partial);
     return e == hipSuccess ? SPC5_OK : hip_fail(e, "spc5_spmv launch");
 }
 
@@ -387,7 +465,10 @@ int spc5_spmv_values(const spc5_matrix *A, const void *values, const void *x, vo
     if (st) return st;
     if (!values && A->nnz) return fail(SPC5_EINVAL, "values is NULL");
     DeviceGuard g(A->device);
-    hipError_t e = launch_spmv(A, values ? values : A->val, x, y, (hipStream_t)stream);
+    Scratch sc;
+    if ((st = forward_scratch(A, (hipStream_t)stream, &sc)) != SPC5_OK) return st;
+    hipError_t e = launch_spmv(A, values ? values : A->val, x, y, (hipStream_t)stream,
+                               sc.partial);
     return e == hipSuccess ? SPC5_OK : hip_fail(e, "spc5_spmv_values launch");
 }
 
@@ -400,7 +481,11 @@ int spc5_spmv_transpose_values(const spc5_matrix *A, const void *values, const v
     int st = compute_guard(A, {{ybar, A ? A->nrows : 0}, {xbar, A ? A->ncols : 0}});
     if (st) return st;
     DeviceGuard g(A->device);
-    hipError_t e = A->tr ? launch_transpose_plan(A, values, ybar, xbar, (hipStream_t)stream)
+    Scratch sc;
+    if (A->tr && (st = pool_scratch(A, (hipStream_t)stream,
+                                    kNeedTrPartial | (values ? kNeedTheta : 0), &sc)) != SPC5_OK)
+        return st;
+    hipError_t e = A->tr ? launch_transpose_plan(A, values, ybar, xbar, (hipStream_t)stream, sc)
                          : launch_transpose(A, values ? values : A->val, ybar, xbar,
                                             (hipStream_t)stream);
     return e == hipSuccess ? SPC5_OK : hip_fail(e, "spc5_spmv_transpose launch");

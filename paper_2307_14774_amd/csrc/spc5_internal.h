@@ -7,6 +7,10 @@
 
 #include "spc5.h"
 
+namespace spc5 {
+struct ScratchPool;
+}
+
 struct spc5_matrix {
     int64_t nrows = 0, ncols = 0, nnz = 0, nblocks = 0, npanels = 0;
     int r = 1, c = 1;
@@ -25,7 +29,7 @@ struct spc5_matrix {
     int32_t *panel_val = nullptr;  // [npanels+1], value offset of each panel
     // staged-kernel tile schedule: first panel / block / value of each tile
     int32_t *tile_p = nullptr, *tile_b = nullptr, *tile_v = nullptr;   // [ntiles_staged+1]
-    int32_t *tile_f = nullptr;     // [ntiles_staged+1], 1: piece of a split panel
+    int32_t *tile_f = nullptr;     // [ntiles_staged+1], piece slot + 1 of a piece tile, else 0
     int64_t ntiles_staged = 0;
     int max_tile_values = 0;       // largest tile, in values
     bool staged_ok = false;        // the staged schedule exists
@@ -33,7 +37,7 @@ struct spc5_matrix {
     // panels longer than a tile: panel, first and last piece tile
     int32_t *split_p = nullptr, *split_t0 = nullptr, *split_t1 = nullptr;   // [nsplit]
     int64_t nsplit = 0;
-    void *partial = nullptr;       // [ntiles_staged * r] partial row sums of pieces
+    int64_t npieces = 0;           // piece tiles (their partial row sums: npieces*r values)
     // transposed-product plan (spc5_prepare_transpose): A^T in beta(r,c) and
     // the tables of the two LDS passes that move caller values from A's
     // packed order to A^T's (see transpose_plan.hip)
@@ -41,8 +45,8 @@ struct spc5_matrix {
     uint16_t *tr_lidx = nullptr;   // [nnz] pass 1: chunk-local value to write
     int32_t *tr_gpos = nullptr;    // [nnz] pass 1: staging slot written
     uint16_t *tr_src = nullptr;    // [nnz] pass 2: bucket-local slot read
-    void *tr_stage = nullptr;      // [nnz] staging buffer
-    void *tr_vals = nullptr;       // [nnz] caller values in A^T's packed order
+    // per-stream scratch of the products (see Scratch)
+    spc5::ScratchPool *pool = nullptr;
 };
 
 struct spc5_csr {
@@ -76,11 +80,32 @@ int validate_csr(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int3
 // Forward kernel picked from the panel statistics of A.
 int auto_kernel(const spc5_matrix *A);
 
-// Forward product; `val` overrides the matrix's packed values when non-null.
+// Scratch memory of one product call: the partial row sums of the piece
+// tiles of A (npieces*r values) and of A^T's plan, and the two buffers that
+// move caller values into A^T's packed order (nnz values each).  A call
+// writes all of it before reading it, so nothing needs clearing.  The normal
+// entry points take it from a pool of the handle with one set per stream
+// (calls on one stream are ordered, calls on different streams do not
+// share); the allocation-free entry point takes a fixed device array.
+struct Scratch {
+    void *partial = nullptr;
+    void *tr_partial = nullptr;
+    void *stage = nullptr;
+    void *vals = nullptr;
+};
+constexpr int kNeedPartial = 1, kNeedTrPartial = 2, kNeedTheta = 4;
+// Scratch of A for stream s with the parts `need` asks for, allocated on the
+// stream's first call that needs them.
+int pool_scratch(const spc5_matrix *A, hipStream_t s, int need, Scratch *out);
+void free_pool(spc5_matrix *A);
+
+// Forward product; `val` overrides the matrix's packed values when non-null;
+// `partial` receives the piece tiles' row sums (A->npieces*r values, unused
+// when A has no piece tiles).
 hipError_t launch_spmv(const spc5_matrix *A, const void *val, const void *x, void *y,
-                       hipStream_t s);
+                       hipStream_t s, void *partial);
 hipError_t launch_spmv_staged(const spc5_matrix *A, const void *val, const void *x, void *y,
-                              hipStream_t s, int remap);
+                              hipStream_t s, int remap, void *partial);
 // (Re)build the staged kernel's tile schedule with at most ppw panels per tile
 // (0: as many as one workgroup has rows for), for a launch of the matrix
 // alone (small matrices: narrower tiles) or for the persistent batch kernel
@@ -111,8 +136,9 @@ int finish_matrix(spc5_matrix *A);
 // Transposed-product plan of A (see spc5_prepare_transpose).
 int build_transpose_plan(spc5_matrix *A, int r, int c);
 // x_out = A^T y_in through the plan; vals overrides A's values (packed order).
+// sc.tr_partial serves A^T's piece tiles, sc.stage and sc.vals the value move.
 hipError_t launch_transpose_plan(const spc5_matrix *A, const void *vals, const void *ybar,
-                                 void *xbar, hipStream_t s);
+                                 void *xbar, hipStream_t s, const Scratch &sc);
 
 // Fill `n` elements of a device array with zero using a kernel (safe to
 // record in a graph).

@@ -308,9 +308,9 @@ static hipError_t dispatch(const spc5_matrix *A, const void *val, const void *x,
 }
 
 hipError_t launch_spmv(const spc5_matrix *A, const void *val, const void *x, void *y,
-                       hipStream_t s) {
+                       hipStream_t s, void *partial) {
     if (A->kernel == SPC5_KERNEL_STAGED)
-        return launch_spmv_staged(A, val ? val : A->val, x, y, s, remap_enabled());
+        return launch_spmv_staged(A, val ? val : A->val, x, y, s, remap_enabled(), partial);
     return A->dtype == SPC5_F64 ? dispatch<double>(A, val, x, y, s)
                                 : dispatch<float>(A, val, x, y, s);
 }

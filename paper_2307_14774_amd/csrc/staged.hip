@@ -36,6 +36,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
+#include <vector>
 
 namespace spc5 {
 
@@ -303,7 +304,7 @@ __attribute__((amdgpu_waves_per_eu(stream_residency<T, R, C, NVG, VAR>()))) void
                                                           s_red);
         if (lead) {
             const int64_t row = (int64_t)(p0 + pl) * R + i;
-            if (f0) partial[t * R + i] = accs;    // summed by k_split_fixup
+            if (f0) partial[(f0 - 1) * R + i] = accs;    // piece slot: k_split_fixup
             else if (row < nrows) y[row] = accs;
         }
         f0 = g0; p0 = q0; p1 = q1; b0 = c0; b1 = c1; v0 = w0; v1 = w1;
@@ -471,7 +472,7 @@ __attribute__((amdgpu_waves_per_eu(vstream_residency<T, C, NVG>()))) void k_spmv
             [&](int v, T *acc) { acc[0] += sval[v]; },
             [&](int pl, const T *acc) {
                 const int64_t row = (int64_t)(p0 + pl);
-                if (f0) partial[t] = acc[0];        // summed by k_split_fixup
+                if (f0) partial[f0 - 1] = acc[0];    // piece slot: k_split_fixup
                 else if (row < nrows) y[row] = acc[0];
             },
             s_long, &s_nlong);
@@ -566,14 +567,16 @@ __global__ void k_tile_sentinel(int64_t npanels, int64_t ntiles, const int32_t *
     tf[ntiles] = 0;
 }
 
-// Rows of a split panel: the partial sums of its pieces.  One wavefront per
-// row (a hub row can have hundreds of pieces): lane l adds pieces l, l+64, ...
-// in tile order, then a butterfly; the order is fixed, so the result is
-// reproducible.
+// Rows of a split panel: the partial sums of its pieces.  The pieces of
+// split panel s are the consecutive tiles st0[s]..st1[s], whose piece slots
+// (tile_f - 1) are consecutive too.  One wavefront per row (a hub row can
+// have hundreds of pieces): lane l adds pieces l, l+64, ... in tile order,
+// then a butterfly; the order is fixed, so the result is reproducible.
 template <typename T>
 __global__ __launch_bounds__(256) void k_split_fixup(int64_t nsplit, int r, int64_t nrows,
                                                      const int32_t *sp, const int32_t *st0,
-                                                     const int32_t *st1, const T *partial, T *y) {
+                                                     const int32_t *st1, const int32_t *tile_f,
+                                                     const T *partial, T *y) {
     const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     if (q >= nsplit * r) return;    // uniform over the wavefront
     const int lane = lane_id();
@@ -581,8 +584,10 @@ __global__ __launch_bounds__(256) void k_split_fixup(int64_t nsplit, int r, int6
     const int i = (int)(q % r);
     const int64_t row = (int64_t)sp[s] * r + i;
     if (row >= nrows) return;
+    const int64_t t0 = st0[s], slot0 = (int64_t)tile_f[t0] - 1;
     T acc = T(0);
-    for (int64_t t = st0[s] + lane; t <= st1[s]; t += kWave) acc += partial[t * r + i];
+    for (int64_t t = t0 + lane; t <= st1[s]; t += kWave)
+        acc += partial[(slot0 + t - t0) * r + i];
     for (int d = 1; d < kWave; d <<= 1) acc += __shfl_xor(acc, d);
     if (lane == 0) y[row] = acc;
 }
@@ -620,10 +625,9 @@ void free_staged_schedule(spc5_matrix *A) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
     }
-    if (A->partial) (void)hipFree(A->partial);
-    A->partial = nullptr;
     A->ntiles_staged = 0;
     A->nsplit = 0;
+    A->npieces = 0;
 }
 
 int build_staged_schedule(spc5_matrix *A, int ppw_req, bool alone) {
@@ -711,16 +715,13 @@ int build_staged_schedule(spc5_matrix *A, int ppw_req, bool alone) {
         return fail(SPC5_EUNSUPPORTED, "too many tiles");
     }
     const size_t nt1 = (size_t)ntiles + 1, ns1 = (size_t)std::max<int64_t>(nsplit, 1);
-    const int vb = A->dtype == SPC5_F64 ? 8 : 4;
     if ((e = hipMalloc((void **)&A->tile_p, nt1 * 4 + kPad)) != hipSuccess ||
         (e = hipMalloc((void **)&A->tile_b, nt1 * 4 + kPad)) != hipSuccess ||
         (e = hipMalloc((void **)&A->tile_v, nt1 * 4 + kPad)) != hipSuccess ||
         (e = hipMalloc((void **)&A->tile_f, nt1 * 4 + kPad)) != hipSuccess ||
         (e = hipMalloc((void **)&A->split_p, ns1 * 4)) != hipSuccess ||
         (e = hipMalloc((void **)&A->split_t0, ns1 * 4)) != hipSuccess ||
-        (e = hipMalloc((void **)&A->split_t1, ns1 * 4)) != hipSuccess ||
-        (nsplit > 0 &&
-         (e = hipMalloc(&A->partial, nt1 * (size_t)A->r * vb)) != hipSuccess))
+        (e = hipMalloc((void **)&A->split_t1, ns1 * 4)) != hipSuccess)
         return bail(e, "allocating the tile schedule");
     launch_tile_groups(grid, 1, A, ppw, vt, bt, vpre, nullptr, first, nullptr, sfirst, A->tile_p,
                        A->tile_b, A->tile_v, A->tile_f, A->split_p, A->split_t0, A->split_t1,
@@ -731,9 +732,23 @@ int build_staged_schedule(spc5_matrix *A, int ppw_req, bool alone) {
     if ((e = hipGetLastError()) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess ||
         (e = hipMemcpy(&hmax, maxv, 4, hipMemcpyDeviceToHost)) != hipSuccess)
         return bail(e, "filling the tile schedule");
+    // piece slots: the pieces numbered in tile order, tile_f = slot + 1, so
+    // that their partial row sums take npieces*r values rather than one row
+    // set per tile
+    int64_t npieces = 0;
+    if (nsplit > 0) {
+        std::vector<int32_t> tf(nt1);
+        if ((e = hipMemcpy(tf.data(), A->tile_f, nt1 * 4, hipMemcpyDeviceToHost)) != hipSuccess)
+            return bail(e, "numbering the piece tiles");
+        for (size_t t = 0; t < (size_t)ntiles; ++t)
+            if (tf[t]) tf[t] = (int32_t)++npieces;
+        if ((e = hipMemcpy(A->tile_f, tf.data(), nt1 * 4, hipMemcpyHostToDevice)) != hipSuccess)
+            return bail(e, "numbering the piece tiles");
+    }
     A->max_tile_values = hmax;
     A->ntiles_staged = ntiles;
     A->nsplit = nsplit;
+    A->npieces = npieces;
     cleanup();
     return SPC5_OK;
 }
@@ -742,7 +757,7 @@ int build_staged_schedule(spc5_matrix *A, int ppw_req, bool alone) {
 
 template <typename T, int R, int C, int NVG, bool SPARSE, int VAR = 0>
 static hipError_t launch_stream_g(const spc5_matrix *A, const T *val, const T *x, T *y,
-                                  hipStream_t s, int remap) {
+                                  hipStream_t s, int remap, T *partial) {
     const int64_t nt = A->ntiles_staged;
     if (nt == 0) return hipSuccess;
     // consecutive tiles per workgroup, the next one always prefetched: 8 on
@@ -760,19 +775,17 @@ static hipError_t launch_stream_g(const spc5_matrix *A, const T *val, const T *x
         hipLaunchKernelGGL((k_spmv_vstream<T, C, NVG>), dim3((unsigned)nwg), dim3(kWG), 0, s,
                            A->nrows, A->ncols, nt, tpw, nwg, remap, A->tile_p, A->tile_b,
                            A->tile_v, A->tile_f, A->blk_ptr, A->blk_col,
-                           (const typename MaskOf<C>::type *)A->masks, val, x, y,
-                           (T *)A->partial);
+                           (const typename MaskOf<C>::type *)A->masks, val, x, y, partial);
     else
         hipLaunchKernelGGL((k_spmv_stream<T, R, C, NVG, SPARSE, VAR>), dim3((unsigned)nwg), dim3(kWG),
                            0, s, A->nrows, A->ncols, nt, tpw, nwg, remap, A->tile_p, A->tile_b,
                            A->tile_v, A->tile_f, A->blk_ptr, A->blk_col,
-                           (const typename MaskOf<C>::type *)A->masks, val, x, y,
-                           (T *)A->partial);
+                           (const typename MaskOf<C>::type *)A->masks, val, x, y, partial);
     if (A->nsplit > 0) {
         const int64_t n = A->nsplit * R * kWave;    // a wavefront per row
         hipLaunchKernelGGL(k_split_fixup<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                            A->nsplit, R, A->nrows, A->split_p, A->split_t0, A->split_t1,
-                           (const T *)A->partial, y);
+                           A->tile_f, (const T *)partial, y);
     }
     return hipGetLastError();
 }
@@ -793,50 +806,57 @@ static bool sparse_rows(const spc5_matrix *A) {
 // KiB (value-mode tiles at most value_tile() values).
 template <typename T, int R, int C, bool SPARSE>
 static hipError_t launch_stream_s(const spc5_matrix *A, const T *val, const T *x, T *y,
-                                  hipStream_t s, int remap) {
+                                  hipStream_t s, int remap, T *partial) {
     const int64_t need = (int64_t)A->max_tile_values * (int64_t)sizeof(T) + 16;
-    if (need <= 4096) return launch_stream_g<T, R, C, 1, SPARSE>(A, val, x, y, s, remap);
-    if (need <= 8192) return launch_stream_g<T, R, C, 2, SPARSE>(A, val, x, y, s, remap);
+    if (need <= 4096)
+        return launch_stream_g<T, R, C, 1, SPARSE>(A, val, x, y, s, remap, partial);
+    if (need <= 8192)
+        return launch_stream_g<T, R, C, 2, SPARSE>(A, val, x, y, s, remap, partial);
     // a 12 KiB buffer where the tiles fit: one more resident workgroup per
     // compute unit (FP64 beta(4,4) Laplacian: 6 instead of 5)
-    if (need <= 12288) return launch_stream_g<T, R, C, 3, SPARSE>(A, val, x, y, s, remap);
+    if (need <= 12288)
+        return launch_stream_g<T, R, C, 3, SPARSE>(A, val, x, y, s, remap, partial);
     // value-mode tiles stop at value_tile() values (8 or 12 KiB)
     if constexpr (R == 1) return hipErrorInvalidValue;
-    else return launch_stream_g<T, R, C, 4, SPARSE>(A, val, x, y, s, remap);
+    else return launch_stream_g<T, R, C, 4, SPARSE>(A, val, x, y, s, remap, partial);
 }
 
 template <typename T, int R, int C>
 static hipError_t launch_stream(const spc5_matrix *A, const T *val, const T *x, T *y,
-                                hipStream_t s, int remap) {
+                                hipStream_t s, int remap, T *partial) {
     // ablation variants: compiled for the paper's main shapes only
     constexpr bool kVarShape = (R == 2 || R == 4 || R == 8) && (C == 4 || C == 8);
     if (A->variant != 0) {
         if constexpr (kVarShape) {
             switch (A->variant) {
                 case kVarPartialX:
-                    return launch_stream_g<T, R, C, 4, false, kVarPartialX>(A, val, x, y, s, remap);
+                    return launch_stream_g<T, R, C, 4, false, kVarPartialX>(A, val, x, y, s,
+                                                                           remap, partial);
                 case kVarRowReduce:
                     return launch_stream_g<T, R, C, 4, false, kVarRowReduce>(A, val, x, y, s,
-                                                                            remap);
+                                                                            remap, partial);
                 default:
                     return launch_stream_g<T, R, C, 4, false, kVarPartialX | kVarRowReduce>(
-                        A, val, x, y, s, remap);
+                        A, val, x, y, s, remap, partial);
             }
         }
         return hipErrorInvalidValue;
     }
-    if constexpr (R == 1) return launch_stream_s<T, R, C, false>(A, val, x, y, s, remap);
+    if constexpr (R == 1)
+        return launch_stream_s<T, R, C, false>(A, val, x, y, s, remap, partial);
     else
-        return sparse_rows(A) ? launch_stream_s<T, R, C, true>(A, val, x, y, s, remap)
-                              : launch_stream_s<T, R, C, false>(A, val, x, y, s, remap);
+        return sparse_rows(A)
+                   ? launch_stream_s<T, R, C, true>(A, val, x, y, s, remap, partial)
+                   : launch_stream_s<T, R, C, false>(A, val, x, y, s, remap, partial);
 }
 
 template <typename T>
 static hipError_t staged_dispatch(const spc5_matrix *A, const void *val, const void *x, void *y,
-                                  hipStream_t s, int remap) {
+                                  hipStream_t s, int remap, void *partial) {
 #define SPC5_CASE(RR, CC)                                                                    \
     case RR * 100 + CC:                                                                     \
-        return launch_stream<T, RR, CC>(A, (const T *)val, (const T *)x, (T *)y, s, remap);
+        return launch_stream<T, RR, CC>(A, (const T *)val, (const T *)x, (T *)y, s, remap, \
+                                        (T *)partial);
 #define SPC5_ROW(RR) SPC5_CASE(RR, 4) SPC5_CASE(RR, 8) SPC5_CASE(RR, 16)
     switch (A->r * 100 + (A->c <= 4 ? 4 : (A->c <= 8 ? 8 : 16))) {
         SPC5_ROW(1) SPC5_ROW(2) SPC5_ROW(3) SPC5_ROW(4)
@@ -848,10 +868,11 @@ static hipError_t staged_dispatch(const spc5_matrix *A, const void *val, const v
 }
 
 hipError_t launch_spmv_staged(const spc5_matrix *A, const void *val, const void *x, void *y,
-                              hipStream_t s, int remap) {
+                              hipStream_t s, int remap, void *partial) {
     if (!A->staged_ok) return hipErrorInvalidValue;
-    return A->dtype == SPC5_F64 ? staged_dispatch<double>(A, val, x, y, s, remap)
-                                : staged_dispatch<float>(A, val, x, y, s, remap);
+    if (A->npieces > 0 && !partial) return hipErrorInvalidValue;
+    return A->dtype == SPC5_F64 ? staged_dispatch<double>(A, val, x, y, s, remap, partial)
+                                : staged_dispatch<float>(A, val, x, y, s, remap, partial);
 }
 
 }  // namespace spc5

@@ -203,14 +203,14 @@ __global__ __launch_bounds__(kMoveThreads) void k_move_buckets(int64_t n,
 }
 
 template <typename T>
-static void launch_move(const spc5_matrix *A, const T *vals, hipStream_t s) {
+static void launch_move(const spc5_matrix *A, const T *vals, hipStream_t s, T *stage, T *out) {
     constexpr int64_t W = kMoveValues;
     const int64_t n = A->nnz;
     const unsigned grid = (unsigned)((n + W - 1) / W);
     hipLaunchKernelGGL(k_move_chunks<T>, dim3(grid), dim3(kMoveThreads), 0, s, n, A->tr_lidx,
-                       A->tr_gpos, vals, (T *)A->tr_stage);
+                       A->tr_gpos, vals, stage);
     hipLaunchKernelGGL(k_move_buckets<T>, dim3(grid), dim3(kMoveThreads), 0, s, n, A->tr_src,
-                       (const T *)A->tr_stage, (T *)A->tr_vals);
+                       (const T *)stage, out);
 }
 
 int build_transpose_plan(spc5_matrix *A, int r, int c) {
@@ -225,7 +225,6 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     spc5_matrix *T = nullptr;
     int32_t *perm = nullptr;
     uint16_t *lidx = nullptr, *src = nullptr;
-    void *gbuf = nullptr, *stage = nullptr;
     size_t tmp_bytes = 0;
     auto cleanup = [&]() {
         for (void *p : {(void *)row_of, (void *)col_of, (void *)key_s, (void *)idx_s,
@@ -235,7 +234,7 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     auto fail_all = [&](int st) {
         cleanup();
         free_matrix(T);
-        for (void *p : {(void *)perm, (void *)lidx, (void *)src, gbuf, stage})
+        for (void *p : {(void *)perm, (void *)lidx, (void *)src})
             if (p) (void)hipFree(p);
         return st;
     };
@@ -300,8 +299,7 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     T->mask_bytes = c <= 8 ? 1 : 2;
     T->npanels = (T->nrows + r - 1) / r;
     T->device = A->device;
-    if ((e = hipMalloc((void **)&perm, nz * 4 + kPad)) != hipSuccess ||
-        (e = hipMalloc(&gbuf, nz * vb + kPad)) != hipSuccess)
+    if ((e = hipMalloc((void **)&perm, nz * 4 + kPad)) != hipSuccess)
         return fail_all(hip_fail(e, "allocating the transpose plan"));
     int st = convert_on_device(T, rowptr_t, colidx_t, val_t, idx_s, perm);
     if (st != SPC5_OK) return fail_all(st);
@@ -311,8 +309,7 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     // bucket of their A^T position; pass 1's lists: a stable sort of the
     // slots by the chunk of A they read.
     if ((e = hipMalloc((void **)&lidx, nz * 2 + kPad)) != hipSuccess ||
-        (e = hipMalloc((void **)&src, nz * 2 + kPad)) != hipSuccess ||
-        (e = hipMalloc(&stage, nz * vb + kPad)) != hipSuccess)
+        (e = hipMalloc((void **)&src, nz * 2 + kPad)) != hipSuccess)
         return fail_all(hip_fail(e, "allocating the transpose plan"));
     if (nnz > 0) {
         const int64_t w = kMoveValues;
@@ -355,24 +352,26 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     A->tr_lidx = lidx;
     A->tr_gpos = perm;
     A->tr_src = src;
-    A->tr_stage = stage;
-    A->tr_vals = gbuf;
     return SPC5_OK;
 }
 
 hipError_t launch_transpose_plan(const spc5_matrix *A, const void *vals, const void *ybar,
-                                 void *xbar, hipStream_t s) {
+                                 void *xbar, hipStream_t s, const Scratch &sc) {
     const spc5_matrix *T = A->tr;
     const void *tv = T->val;
     if (vals && A->nnz > 0) {
         // the caller's values (A's packed order) moved to A^T's packed order
-        if (A->dtype == SPC5_F64) launch_move<double>(A, (const double *)vals, s);
-        else launch_move<float>(A, (const float *)vals, s);
+        if (!sc.stage || !sc.vals) return hipErrorInvalidValue;
+        if (A->dtype == SPC5_F64)
+            launch_move<double>(A, (const double *)vals, s, (double *)sc.stage,
+                                (double *)sc.vals);
+        else
+            launch_move<float>(A, (const float *)vals, s, (float *)sc.stage, (float *)sc.vals);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        tv = A->tr_vals;
+        tv = sc.vals;
     }
-    return launch_spmv(T, tv, ybar, xbar, s);
+    return launch_spmv(T, tv, ybar, xbar, s, sc.tr_partial);
 }
 
 }  // namespace spc5

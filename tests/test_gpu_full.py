@@ -97,3 +97,85 @@ def test_full_size_fem(rc, dtype, tol, dev):
     say(f"full fem96 beta{rc} {dtype}")
     _, _, err = check(A, *rc, dev, dtype)
     assert err <= tol, err
+
+
+def test_full_size_fem_conversion(dev):
+    """FEM 96^3 x 3 (210.5 M nonzeros) converted on the device: bit-exact
+    against the oracle's greedy conversion and equal to the closed-form
+    block counts (beta(1,8) 46,623,720; beta(2,4) 35,172,280; beta(4,4)
+    17,667,936)."""
+    from helpers import fem_block_count
+    from paper_2307_14774_amd import spc5 as S
+    A = workload("fem96")
+    closed = {(1, 8): 46_623_720, (2, 4): 35_172_280, (4, 4): 17_667_936}
+    for (r, c), nb in closed.items():
+        say(f"full fem96 conversion beta({r},{c})")
+        assert fem_block_count(96, r, c) == nb
+        M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+        assert M.info.nblocks == nb
+        bp, bc, mk, va = M.export()
+        M.free()
+        O = oracle.csr_to_spc5(A.rowptr, A.colidx, A.values, A.ncols, r, c)
+        assert O.nblocks == nb
+        assert np.array_equal(bp, O.blk_ptr) and np.array_equal(bc, O.blk_col)
+        assert np.array_equal(mk.astype(np.uint16), O.masks)
+        assert np.array_equal(va.view(np.uint64), O.values.view(np.uint64))
+        del bp, bc, mk, va, O
+
+
+_batch_cache = {}
+
+
+def batch_workload():
+    """The 256 uneven matrices of the batched workload (rows log-uniform in
+    1k..200k, Zipf(1.5) row lengths capped at 512, 30% of nonzeros in runs)."""
+    if "mats" not in _batch_cache:
+        _batch_cache["mats"] = W.batch_of_runs(256, seed=0)
+    return _batch_cache["mats"]
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_full_size_batch_256(dtype, dev):
+    """The batched workload at its stated size in the configuration the
+    benchmark times: all 256 matrices, shapes from the autotuner, one
+    persistent launch per k in {1, 4, 16}; every matrix's Y against the FP64
+    oracle (CSR SpMM), relative L2 <= 1e-14 (FP64) / 1e-6 (FP32, against the
+    oracle on the FP32-rounded data)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_2307_14774_amd import autotune
+    from paper_2307_14774_amd import spc5 as S
+    mats = batch_workload()
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    say(f"full batch 256 {dtype}: converting")
+    Ms = []
+    for A in mats:
+        (r, c), _ = autotune.choose_shape(A, dtype)
+        Ms.append(S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c, dtype))
+    B = S.Spc5Batch(Ms)
+    if dtype == "float64":
+        vals = [A.values for A in mats]
+    else:
+        vals = [A.values.astype(np.float32).astype(np.float64) for A in mats]
+    for k in (1, 4, 16):
+        say(f"full batch 256 {dtype} k={k}")
+        rng = np.random.default_rng(1000 + k)
+        Xh = [rng.uniform(-1, 1, (A.ncols, k)) for A in mats]
+        if dtype == "float32":
+            Xh = [X.astype(np.float32).astype(np.float64) for X in Xh]
+        Ys = B.spmm([torch.tensor(X, dtype=tdt, device=dev) for X in Xh])
+        torch.cuda.synchronize()
+        Yh = [Y.cpu().double().numpy() for Y in Ys]
+        del Ys
+
+        def err(m):
+            A = mats[m]
+            return oracle.rel_l2(Yh[m], oracle.csr_spmm(A.rowptr, A.colidx, vals[m], Xh[m]))
+        with ThreadPoolExecutor(8) as ex:
+            errs = list(ex.map(err, range(len(mats))))
+        worst = int(np.argmax(errs))
+        say(f"  worst rel L2 {errs[worst]:.3e} (matrix {worst})")
+        assert errs[worst] <= (1e-14 if dtype == "float64" else 1e-6), (worst, errs[worst])
+    B.free()
+    for M in Ms:
+        M.free()

@@ -16,8 +16,13 @@ from paper_2307_14774_amd import workloads as W
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
+# every (r, c-class) instantiation of the kernels: r in 1..8 with c <= 4,
+# c <= 8 and c <= 16, plus odd c inside a class; beta(2,16), beta(4,16) and
+# beta(8,16) are the paper's FP32 beta(r,VS) shapes (Section 4.2)
 SHAPES = [(1, 8), (2, 4), (4, 4), (1, 16), (2, 8), (4, 8), (8, 8), (8, 4), (3, 5),
-          (1, 1), (5, 16), (7, 3), (6, 12), (2, 2), (1, 4)]
+          (1, 1), (5, 16), (7, 3), (6, 12), (2, 2), (1, 4),
+          (2, 16), (3, 4), (3, 16), (4, 16), (5, 4), (5, 8), (6, 4), (6, 8), (7, 8),
+          (7, 16), (8, 16)]
 MAIN = [(1, 8), (2, 4), (4, 4)]
 
 
@@ -285,19 +290,36 @@ def test_spmv_overwrites_y(dev):
     assert oracle.rel_l2(y, oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)) <= 1e-14
 
 
+def aggregate_condition(A):
+    """kappa = || |A| |x| || / || A x ||: how much the rows' cancellation
+    amplifies rounding in the relative L2 error."""
+    yref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
+    yabs = oracle.csr_spmv(A.rowptr, A.colidx, np.abs(A.values), np.abs(A.x))
+    den = float(np.linalg.norm(yref))
+    return float(np.linalg.norm(yabs)) / den if den > 0.0 else 1.0
+
+
 @pytest.mark.parametrize("A", CASES[8:], ids=lambda a: a.name)
-@pytest.mark.parametrize("rc", MAIN + [(1, 16), (4, 8)], ids=lambda t: "b%d_%d" % t)
+@pytest.mark.parametrize("rc", SHAPES, ids=lambda t: "b%d_%d" % t)
 @pytest.mark.parametrize("kernel", ["staged", "rows", "sweep"])
 def test_spmv_f32(A, rc, kernel, dev):
     r, c = rc
     say(f"spmv f32 {A.name} beta{rc} {kernel}")
     _, y = run_spmv(A, r, c, dev, "float32", kernel=kernel)
     yref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
-    if not A.name.startswith("rand11x6000"):
-        # the 1e-6 gate on workload-shaped matrices; the 11-row case sums
-        # 4800-term rows with heavy cancellation, beyond what an FP32
-        # accumulation can resolve to 1e-6: it is held to the bound below
-        assert oracle.rel_l2(y, yref) <= 1e-6
+    err = oracle.rel_l2(y, yref)
+    kappa = aggregate_condition(A)
+    if kappa <= 20.0:
+        # the 1e-6 gate on well-conditioned, workload-shaped matrices
+        assert err <= 1e-6
+    else:
+        # rows of thousands of terms with heavy cancellation (the 11-row
+        # case: kappa = 112, rows of 4,800 terms): the error of any FP32
+        # summation grows with kappa; a sequential FP32 sum in order reaches
+        # 1.6e-6 there.  The gate scales with kappa, and the per-row bound
+        # below holds every row to the FP32 forward-error bound.
+        say(f"  f32 rel L2 {err:.3e}, kappa {kappa:.1f}")
+        assert err <= 1e-6 * kappa / 20.0
     # accumulation error alone: against the FP64 oracle on FP32-rounded data
     v32 = A.values.astype(np.float32).astype(np.float64)
     x32 = A.x.astype(np.float32).astype(np.float64)
@@ -702,6 +724,48 @@ def test_spmv_two_streams(dev):
     torch.cuda.synchronize()
     for q in range(len(xs)):
         assert torch.equal(ys[q], want[q]), q
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_scratch_products_on_two_streams(dtype, dev):
+    """Products that need scratch memory, issued on two streams at once on one
+    handle: forward products of a matrix whose long panels are cut into
+    pieces (partial row sums) and transposes with caller values through a
+    plan (the value move).  Each stream has its own scratch, so every result
+    equals the eager single-stream call bit for bit."""
+    A = long_panel_matrix(27)
+    S = spc5()
+    say(f"scratch products on two streams {dtype}")
+    M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 1, 8, dtype)
+    assert M.info.split_panels > 0
+    M.prepare_transpose(1, 8)
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    rng = np.random.default_rng(35)
+    n = 8
+    xs = [to_dev(rng.uniform(-1, 1, A.ncols), dev, tdt) for _ in range(n)]
+    ws = [to_dev(rng.uniform(-1, 1, A.nrows), dev, tdt) for _ in range(n)]
+    ths = [to_dev(rng.uniform(-1, 1, A.nnz), dev, tdt) for _ in range(n)]
+    want_y = [M.spmv_values(th, x).clone() for th, x in zip(ths, xs)]
+    want_xb = [M.transpose(w, values=th).clone() for th, w in zip(ths, ws)]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    ys = [torch.full((A.nrows,), float("nan"), dtype=tdt, device=dev) for _ in range(n)]
+    xbs = [torch.full((A.ncols,), float("nan"), dtype=tdt, device=dev) for _ in range(n)]
+    for st in streams:
+        st.wait_stream(torch.cuda.current_stream())
+    for q in range(n):
+        st = streams[q % 2]
+        with torch.cuda.stream(st):
+            M.spmv_values(ths[q], xs[q], ys[q], stream=st)
+            M.transpose(ws[q], xbs[q], values=ths[q], stream=st)
+    torch.cuda.synchronize()
+    for q in range(n):
+        assert torch.equal(ys[q], want_y[q]), q
+        assert torch.equal(xbs[q], want_xb[q]), q
+    ref = oracle.csr_spmv(A.rowptr, A.colidx, ths[0].double().cpu().numpy(),
+                          xs[0].double().cpu().numpy())
+    assert oracle.rel_l2(ys[0].double().cpu().numpy(), ref) <= (1e-14 if dtype == "float64"
+                                                                 else 1e-6)
 
 
 @pytest.mark.parametrize("dtype", ["float32", "float64"])
