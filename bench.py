@@ -6,14 +6,16 @@
 A step is one forward product y = A x over the SPC5 beta(r,c) storage (all
 hot-path steps: panel scheduling, metadata stream, mask expansion, value
 stream, x gather, FMA, row reduction and y store) of one seeded synthetic
-matrix already resident in HBM.  The default workload is the 5-point
-Laplacian on a 2048 x 2048 grid in FP64 with beta(4,4).  One JSON line is
-printed: GFLOP/s (2 flops per stored nonzero), the roofline of the forward
-kernel (algorithmic bytes / mean launch time against 8 TB/s), the other
-formats and the plain CSR kernel on the same GPU, the FEM matrix in FP64 and
-FP32, the differentiated product (forward + backward) on the 2^20 Zipf graph,
-the batched SpMM over 256 uneven matrices, and the CPU oracle timed on this
-host as a baseline.  Launch times are means over back-to-back launches
+matrix already resident in HBM.  The default workload is the largest one
+that fits one GPU: the 3D vector-FEM-like matrix on 96^3 nodes x 3 dof
+(2,654,208 rows, 210.5 M nonzeros) in FP64 with beta(4,4).  One JSON line
+is printed: GFLOP/s (2 flops per stored nonzero), the roofline of the
+forward kernel (algorithmic bytes / mean launch time against 8 TB/s), the
+other kernels and formats and the plain CSR kernel on the same matrix, FP32,
+the 2048^2 Laplacian (warm and with the Infinity Cache flushed), the
+differentiated product (forward + backward) on the 2^20 Zipf graph, the
+batched SpMM over 256 uneven matrices, the paper's ablations, and the CPU
+oracle timed on this host as a baseline (one thread and all cores).  Launch times are means over back-to-back launches
 between one HIP event pair on the launching stream (gaps between launches
 included); the cold-cache run alone puts an event pair around every launch,
 so that the flush between launches stays outside the events.
@@ -191,30 +193,64 @@ def traffic_write(fetch_csv, write_csv, workload):
     print(json.dumps(out))
 
 
-def cpu_baseline(A, rc, budget_s=10.0):
-    """The oracle as it stands (scalar Algorithm 1 over its own beta(r,c)
-    conversion, FP64, one thread), on as many full passes as fit the budget."""
+def host_identity():
+    """CPU model name and the number of cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores, os.cpu_count() or 1
+
+
+def cpu_baseline(A, passes=5):
+    """The oracle as it stands, O1 (the CSR definition, FP64, built -O3
+    -ffp-contract=off), timed on this host: one thread, and all the cores
+    this process may use with the rows cut into equal contiguous ranges, one
+    per thread (the paper's naive static split, Section 4.3).  Each leg runs
+    `passes` full passes over the whole matrix after one untimed pass; the
+    median pass is reported."""
+    import numpy as np
+
     import oracle
-    S = oracle.csr_to_spc5(A.rowptr, A.colidx, A.values, A.ncols, *rc)
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        oracle.spc5_spmv(S, A.x)
-        n += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": round(2.0 * A.nnz * n / dt / 1e9, 4), "unit": "GFLOP/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{n} full passes of the scalar Algorithm 1 oracle over the whole matrix "
-                      f"(beta{rc}, FP64, single thread, {dt:.1f} s)"}
+    model, cores, nproc = host_identity()
+
+    def leg(fn):
+        fn()
+        ts = []
+        for _ in range(passes):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), ts
+
+    t1, ts1 = leg(lambda: oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x))
+    tn, tsn = leg(lambda: oracle.csr_spmv_par(A.rowptr, A.colidx, A.values, A.x, cores))
+    gf = lambda t: round(2.0 * A.nnz / t / 1e9, 4)
+    return {"value": gf(tn), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"median of {passes} full passes of O1 (CSR definition, FP64) over the "
+                      f"whole matrix on {cores} threads, rows split evenly; one thread: "
+                      f"median of {passes} passes",
+            "single_thread": {"value": gf(t1), "median_pass_s": round(t1, 4),
+                              "passes_s": [round(t, 4) for t in ts1]},
+            "all_cores": {"value": gf(tn), "threads": cores, "median_pass_s": round(tn, 4),
+                          "passes_s": [round(t, 4) for t in tsn]},
+            "host": {"cpu_model": model, "nproc": nproc, "cores_available": cores}}
 
 
 def fem_extras(dev):
     """3D 3-dof 27-point FEM-like matrix (96^3 nodes, 210.5 M nonzeros): FP64
     and FP32 beta(4,4) and beta(1,8), plain CSR FP64; FP32 error against the
-    FP64 oracle on the original FP64 data."""
-    import numpy as np
+    FP64 oracle on the original FP64 data (used when the timed workload is
+    another matrix)."""
     import torch
 
     import oracle
@@ -250,6 +286,119 @@ def fem_extras(dev):
                           "frac_hbm": round(C.spmv_bytes / avg / 1e9 / PEAK_HBM_GBS, 4),
                           "rel_l2_vs_fp64_oracle": oracle.rel_l2(y.cpu().numpy(), yref)}
     C.free()
+    return res
+
+
+def laplacian_extras(dev, A):
+    """The 2D 5-point Laplacian on a 2048^2 grid (20.96 M nonzeros, 272.6 MB
+    in FP64 beta(4,4), about the size of the 256 MB Infinity Cache): FP64
+    beta(4,4) warm (back-to-back launches) and flushed (a 1 GiB buffer read
+    between launches, outside the timed events), FP32 beta(4,4), and the
+    plain CSR kernel FP64."""
+    import torch
+
+    import oracle
+    from paper_2307_14774_amd import spc5
+    yref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
+    res = {"nrows": A.nrows, "nnz": A.nnz}
+    x = torch.from_numpy(A.x).to(dev)
+    y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+
+    def entry(avg_s, nb, yy):
+        return {"gflops": round(2.0 * A.nnz / avg_s / 1e9, 1), "launch_us": round(avg_s * 1e6, 2),
+                "gbs": round(nb / avg_s / 1e9, 1), "frac_hbm": round(nb / avg_s / 1e9 / PEAK_HBM_GBS, 4),
+                "rel_l2_vs_fp64_oracle": oracle.rel_l2(yy.cpu().double().numpy(), yref)}
+    log("Laplacian fp64 beta(4,4)")
+    M = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 4, 4)
+    nb = M.info.spmv_bytes
+    res["float64 beta(4,4)"] = entry(time_region(lambda: M.spmv(x, y), 200, 100)[1] * 1e-3, nb, y)
+    scratch = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    sink = torch.empty((), dtype=torch.float64, device=dev)
+    _, ms = time_launches(lambda: M.spmv(x, y), 30, 3,
+                          flush=lambda: torch.sum(scratch, dim=0, out=sink))
+    res["float64 beta(4,4) flushed"] = entry(float(sum(ms) / len(ms)) * 1e-3, nb, y)
+    del scratch, sink
+    M.free()
+    log("Laplacian fp32 beta(4,4)")
+    M = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, 4, 4, "float32")
+    x32, y32 = x.float(), torch.empty(A.nrows, dtype=torch.float32, device=dev)
+    res["float32 beta(4,4)"] = entry(time_region(lambda: M.spmv(x32, y32), 200, 100)[1] * 1e-3,
+                                     M.info.spmv_bytes, y32)
+    M.free()
+    log("Laplacian plain CSR fp64")
+    C = spc5.CsrMatrix(A.rowptr, A.colidx, A.values, A.ncols)
+    res["float64 csr"] = entry(time_region(lambda: C.spmv(x, y), 100, 20)[1] * 1e-3,
+                               C.spmv_bytes, y)
+    C.free()
+    res["speedup_vs_csr"] = round(res["float64 csr"]["launch_us"]
+                                  / res["float64 beta(4,4)"]["launch_us"], 3)
+    log("Laplacian rocSPARSE CSR fp64")
+    rs = rocsparse_csr(dev, A, yref)
+    if rs is not None:
+        res["float64 csr rocsparse"] = rs
+        res["speedup_vs_rocsparse_csr"] = round(rs["launch_us"]
+                                                / res["float64 beta(4,4)"]["launch_us"], 3)
+    return res
+
+
+def rocsparse_csr(dev, A, yref, steps=100, warmup=20):
+    """The vendor library's CSR product (rocSPARSE csrmv with its analysis
+    step, FP64) on the same matrix: a run-only yardstick for the plain CSR
+    format next to this library's own CSR kernel.  Returns None when the
+    library cannot be loaded."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import oracle
+    lib = None
+    for name in ("librocsparse.so", "/opt/rocm/lib/librocsparse.so"):
+        try:
+            lib = ctypes.CDLL(name)
+            break
+        except OSError:
+            continue
+    if lib is None:
+        return None
+    P = ctypes.c_void_p
+
+    def ok(st, what):
+        if st != 0:
+            raise RuntimeError(f"rocsparse {what}: status {st}")
+    h, descr, info = P(), P(), P()
+    ok(lib.rocsparse_create_handle(ctypes.byref(h)), "create_handle")
+    ok(lib.rocsparse_set_stream(h, P(torch.cuda.current_stream().cuda_stream)), "set_stream")
+    ok(lib.rocsparse_create_mat_descr(ctypes.byref(descr)), "create_mat_descr")
+    ok(lib.rocsparse_create_mat_info(ctypes.byref(info)), "create_mat_info")
+    m, n, nnz = A.nrows, A.ncols, A.nnz
+    rp = torch.from_numpy(A.rowptr.astype(np.int32)).to(dev)
+    ci = torch.from_numpy(A.colidx).to(dev)
+    va = torch.from_numpy(A.values).to(dev)
+    x = torch.from_numpy(A.x).to(dev)
+    y = torch.empty(m, dtype=torch.float64, device=dev)
+    ptr = lambda t: P(t.data_ptr())
+    op_none = 111
+    lib.rocsparse_dcsrmv_analysis.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int, P, P, P, P, P]
+    lib.rocsparse_dcsrmv.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     P, P, P, P, P, P, P, P, P]
+    ok(lib.rocsparse_dcsrmv_analysis(h, op_none, m, n, nnz, descr, ptr(va), ptr(rp), ptr(ci),
+                                     info), "dcsrmv_analysis")
+    alpha, beta = ctypes.c_double(1.0), ctypes.c_double(0.0)
+    ap_, bp_ = ctypes.cast(ctypes.byref(alpha), P), ctypes.cast(ctypes.byref(beta), P)
+    args = (h, op_none, m, n, nnz, ap_, descr, ptr(va), ptr(rp), ptr(ci), info, ptr(x), bp_,
+            ptr(y))
+    ok(lib.rocsparse_dcsrmv(*args), "dcsrmv")
+    avg = time_region(lambda: lib.rocsparse_dcsrmv(*args), steps, warmup)[1] * 1e-3
+    nb = 8 * nnz + 4 * nnz + 4 * (m + 1) + 8 * n + 8 * m
+    res = {"kernel": "rocsparse_dcsrmv (adaptive, after csrmv_analysis)",
+           "launch_us": round(avg * 1e6, 2), "gflops": round(2.0 * nnz / avg / 1e9, 1),
+           "gbs": round(nb / avg / 1e9, 1), "frac_hbm": round(nb / avg / 1e9 / PEAK_HBM_GBS, 4),
+           "rel_l2_vs_fp64_oracle": oracle.rel_l2(y.cpu().numpy(), yref)}
+    lib.rocsparse_destroy_mat_info(info)
+    lib.rocsparse_destroy_mat_descr(descr)
+    lib.rocsparse_destroy_handle(h)
     return res
 
 
@@ -343,9 +492,13 @@ def backward_extras(dev):
 def batch_extras(dev, nmat=256, ks=(1, 4, 16)):
     """Batched workload: `nmat` uneven matrices (log-uniform 1k..200k rows,
     Zipf(1.5) row lengths capped at 512, 30% of nonzeros in runs), beta(r,c)
-    per matrix from the byte-model autotuner, k right-hand sides, all in one
-    persistent launch; against plain FP64 single SpMVs (CSR kernel and
-    SPC5 FP64 at the same shapes), one launch per matrix and vector."""
+    per matrix from the byte-model autotuner and each matrix's batch tile cap
+    measured by it, k right-hand sides, all in one persistent launch; against
+    plain FP64 single SpMVs (CSR kernel and SPC5 FP64 at the same shapes), one
+    launch per matrix and vector.  Every matrix's Y is checked against the
+    FP64 oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
     import torch
 
@@ -370,7 +523,6 @@ def batch_extras(dev, nmat=256, ks=(1, 4, 16)):
     for C in csrs:
         C.free()
     del csrs
-    check = [int(i) for i in np.random.default_rng(1).choice(nmat, 4, replace=False)]
     for dt, tdt in (("float64", torch.float64), ("float32", torch.float32)):
         log(f"batch: autotune + convert {dt}")
         Ms, shapes = [], {}
@@ -387,36 +539,59 @@ def batch_extras(dev, nmat=256, ks=(1, 4, 16)):
             us_plain = time_region(plain_spc5, 5, 2)[1] * 1e3
             res["plain_fp64_spc5_us_per_vector"] = round(us_plain, 1)
         B = spc5.Spc5Batch(Ms)
+        vb = 8 if dt == "float64" else 4
+        vals = [A.values if dt == "float64" else A.values.astype(np.float32).astype(np.float64)
+                for A in mats]
         for k in ks:
             log(f"batch: {dt} k={k}")
             rng = np.random.default_rng(k)
             Xh = [rng.uniform(-1, 1, (A.ncols, k)) for A in mats]
+            if dt == "float32":
+                Xh = [X.astype(np.float32).astype(np.float64) for X in Xh]
             Xs = [torch.from_numpy(X).to(dev, tdt) for X in Xh]
             Ys = [torch.empty((A.nrows, k), dtype=tdt, device=dev) for A in mats]
             B.set_operands(Xs, Ys)
-            us = time_region(B.run, 10, 3)[1] * 1e3
-            vb = 8 if dt == "float64" else 4
+            us_default = time_region(B.run, 10, 3)[1] * 1e3
+            # per-matrix schedule from the autotuner: each matrix's batch tile
+            # cap timed on a batch of it alone with k right-hand sides
+            log(f"batch: {dt} k={k} tuning the per-matrix schedule")
+            t0 = time.perf_counter()
+            caps = autotune.tune_batch(Ms, k)
+            tune_s = time.perf_counter() - t0
+            Bt = spc5.Spc5Batch(Ms)
+            Bt.set_operands(Xs, Ys)
+            us_tuned = time_region(Bt.run, 10, 3)[1] * 1e3
+            for M in Ms:
+                M.set_batch_schedule(0)
+            use_tuned = us_tuned < us_default
+            us = min(us_tuned, us_default)
+            (Bt if use_tuned else B).run()
+            torch.cuda.synchronize()
+            Bt.free()
             # matrix streamed once per launch + k vectors in and out
             byts = sum(M.info.spmv_bytes - vb * (A.ncols + A.nrows) + k * vb * (A.ncols + A.nrows)
                        for M, A in zip(Ms, mats))
-            errs = []
-            for i in check:
+            Yh = [Y.cpu().double().numpy() for Y in Ys]
+
+            def err(i):
                 A = mats[i]
-                if dt == "float64":
-                    ref = oracle.csr_spmm(A.rowptr, A.colidx, A.values, Xh[i])
-                else:
-                    ref = oracle.csr_spmm(A.rowptr, A.colidx,
-                                          A.values.astype(np.float32).astype(np.float64),
-                                          Xh[i].astype(np.float32).astype(np.float64))
-                errs.append(oracle.rel_l2(Ys[i].cpu().double().numpy(), ref))
+                return oracle.rel_l2(Yh[i], oracle.csr_spmm(A.rowptr, A.colidx, vals[i], Xh[i]))
+            with ThreadPoolExecutor(8) as ex:
+                errs = list(ex.map(err, range(nmat)))
             plain = k * plain_csr_us
+            hist = {}
+            for cp in caps:
+                hist[str(cp)] = hist.get(str(cp), 0) + 1
             res[f"{dt} k={k}"] = {
                 "launch_us": round(us, 1), "gflops": round(2.0 * nnz * k / us / 1e3, 1),
                 "gbs": round(byts / us / 1e3, 1), "frac_hbm": round(byts / us / 1e3 / PEAK_HBM_GBS, 4),
+                "default_schedule_us": round(us_default, 1), "tuned_schedule_us": round(us_tuned, 1),
+                "schedule": "tuned" if use_tuned else "default",
+                "tuned_tile_caps": hist, "tuning_s": round(tune_s, 2),
                 "speedup_vs_plain_fp64_csr": round(plain / us, 2),
                 "speedup_vs_plain_fp64_spc5": round(k * res["plain_fp64_spc5_us_per_vector"] / us, 2),
-                "max_rel_l2_sampled": max(errs), "sampled_matrices": check}
-            del Xs, Ys
+                "max_rel_l2_all_matrices": max(errs)}
+            del Xs, Ys, Yh
         B.free()
         for M in Ms:
             M.free()
@@ -458,9 +633,11 @@ def ablation_extras(dev, A_lap):
             log(f"ablation: variants {name} beta{rc}")
             M = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, *rc)
             row = {}
-            for tag, v in (("single_x+multi_reduce", (False, False)),
-                           ("partial_x", (True, False)), ("per_row_reduce", (False, True)),
-                           ("partial_x+per_row_reduce", (True, True))):
+            for tag, v in (("single_x+multi_reduce", (False, False, False)),
+                           ("partial_x", (True, False, False)),
+                           ("per_row_reduce", (False, True, False)),
+                           ("partial_x+per_row_reduce", (True, True, False)),
+                           ("union_x+multi_reduce", (False, False, True))):
                 M.set_variant(*v)
                 us = one(M, x, y)
                 row[tag] = {"launch_us": round(us, 2),
@@ -504,12 +681,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="laplacian")
+    ap.add_argument("--workload", default="fem")
     ap.add_argument("--no-extras", action="store_true", help="only the primary format")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--cpu-passes", type=int, default=5)
     ap.add_argument("--skip", default="", help="comma list of extras to skip: "
-                    "kernels,formats,csr,flushed,fem,backward,batch,ablation")
+                    "kernels,formats,csr,flushed,other,backward,batch,ablation")
     ap.add_argument("--batch-mats", type=int, default=256)
     ap.add_argument("--calibration-copy", action="store_true",
                     help="before timing, negate a 1 GiB float64 buffer 3 times (a plain "
@@ -599,7 +776,7 @@ def main():
                      "avg_launch_us": round(avg_s * 1e6, 2)},
         "parity_rel_l2": prim["rel_l2"],
     }
-    extras = set() if args.no_extras else {"kernels", "formats", "csr", "flushed", "fem",
+    extras = set() if args.no_extras else {"kernels", "formats", "csr", "flushed", "other",
                                            "backward", "batch", "ablation"} - skip
     if "kernels" in extras:
         prim["kernel"] = M.kernel
@@ -627,21 +804,24 @@ def main():
             formats[f"beta({r},{c})"]["fill"] = round(M2.info.fill, 4)
             formats[f"beta({r},{c})"]["kernel"] = M2.kernel
             M2.free()
-        # FP32 storage and accumulation at the same shape (error against the
-        # FP64 oracle on the original FP64 data)
-        log(f"timing float32 beta{rc}")
-        M3 = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, *rc, "float32")
+        # FP32 storage and accumulation (error against the FP64 oracle on the
+        # original FP64 data): the timed shape and the paper's FP32
+        # beta(r,VS) shapes (VS = 16)
         x32 = x.float()
         y32 = torch.empty(A.nrows, dtype=torch.float32, device=dev)
-        us32 = time_region(lambda: M3.spmv(x32, y32), 50, 5)[1] * 1e3
-        formats[f"float32 beta({rc[0]},{rc[1]})"] = {
-            "gflops": round(flops / us32 / 1e3, 2), "launch_us": round(us32, 2),
-            "gbs": round(M3.info.spmv_bytes / us32 / 1e3, 1),
-            "frac_hbm": round(M3.info.spmv_bytes / us32 / 1e3 / PEAK_HBM_GBS, 4),
-            "bytes": int(M3.info.spmv_bytes),
-            "rel_l2_vs_fp64_oracle": oracle.rel_l2(y32.cpu().numpy(), yref),
-            "speedup_vs_fp64": round(prim["launch_us"] / us32, 3)}
-        M3.free()
+        for (r, c) in [rc, (4, 8), (1, 16), (2, 16), (4, 16), (8, 16)]:
+            log(f"timing float32 beta({r},{c})")
+            M3 = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c, "float32")
+            us32 = time_region(lambda: M3.spmv(x32, y32), 50, 5)[1] * 1e3
+            formats[f"float32 beta({r},{c})"] = {
+                "gflops": round(flops / us32 / 1e3, 2), "launch_us": round(us32, 2),
+                "gbs": round(M3.info.spmv_bytes / us32 / 1e3, 1),
+                "frac_hbm": round(M3.info.spmv_bytes / us32 / 1e3 / PEAK_HBM_GBS, 4),
+                "bytes": int(M3.info.spmv_bytes), "fill": round(M3.info.fill, 4),
+                "kernel": M3.kernel,
+                "rel_l2_vs_fp64_oracle": oracle.rel_l2(y32.cpu().numpy(), yref),
+                "speedup_vs_fp64_timed_shape": round(prim["launch_us"] / us32, 3)}
+            M3.free()
         out["formats"] = formats
     if "csr" in extras:
         log("timing plain CSR")
@@ -649,7 +829,12 @@ def main():
         out["csr"] = measure(C, 50, 5, C.spmv_bytes)[0]
         C.free()
         out["speedup_vs_csr"] = round(out["csr"]["launch_us"] / prim["launch_us"], 3)
-    if "flushed" in extras:
+        log("timing rocSPARSE CSR")
+        rs = rocsparse_csr(dev, A, yref)
+        if rs is not None:
+            out["csr_rocsparse"] = rs
+            out["speedup_vs_rocsparse_csr"] = round(rs["launch_us"] / prim["launch_us"], 3)
+    if "flushed" in extras and args.workload == "laplacian":
         # cold-cache figure: a 1 GiB buffer is read between launches (outside
         # the timed events), so the matrix cannot stay in the 256 MB Infinity
         # Cache; reading (not writing) leaves clean lines behind, so the timed
@@ -660,17 +845,27 @@ def main():
                                  flush=lambda: torch.sum(scratch, dim=0, out=sink))[0]
         del scratch, sink
     M.free()
-    if "fem" in extras and args.workload == "laplacian":
-        out["fem"] = fem_extras(dev)
+    A_lap = None
+    if "other" in extras:
+        if args.workload == "laplacian":
+            out["fem"] = fem_extras(dev)
+        else:
+            from paper_2307_14774_amd import workloads as W
+            log("generating the Laplacian workload")
+            A_lap = W.laplacian_2d(2048, seed=0)
+            out["laplacian"] = laplacian_extras(dev, A_lap)
     if "backward" in extras:
         out["backward"] = backward_extras(dev)
     if "batch" in extras:
         out["batch"] = batch_extras(dev, args.batch_mats)
     if "ablation" in extras:
-        out["ablation"] = ablation_extras(dev, A)
+        if A_lap is None:
+            from paper_2307_14774_amd import workloads as W
+            A_lap = A if args.workload == "laplacian" else W.laplacian_2d(2048, seed=0)
+        out["ablation"] = ablation_extras(dev, A_lap)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(A, rc, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(A, args.cpu_passes)
     print(json.dumps(out), flush=True)
 
 

@@ -181,11 +181,16 @@ int spc5_set_schedule(spc5_matrix *A, int kernel, int panels_per_tile);
  *      sums of a row are added one after the other through LDS, instead of
  *      the default multi-reduction (one cross-lane butterfly reducing every
  *      row of the tile together).
+ *  SPC5_VARIANT_UNION_X     x load by the merged row predicates (Section
+ *      3.1's third option): the single x load per block reads only the
+ *      16-byte pieces of the window that hold a column some row of the block
+ *      uses, instead of the whole window; not combined with the others.
  * Results stay within the accuracy of the default (summation order only).
  * Errors: SPC5_EINVAL (NULL A, unknown flags), SPC5_EUNSUPPORTED (the matrix
  * does not use the staged kernel, or r not in {2,4,8}, or c > 8). */
 #define SPC5_VARIANT_PARTIAL_X 1
 #define SPC5_VARIANT_ROW_REDUCE 2
+#define SPC5_VARIANT_UNION_X 4
 int spc5_set_variant(spc5_matrix *A, int flags);
 
 /* ---------------------------------------------------------------- compute */
@@ -258,6 +263,17 @@ int spc5_spmm(const spc5_matrix *A, int nrhs, const void *X, void *Y, void *stre
  * Synchronous. */
 int spc5_batch_create(int nmat, spc5_matrix *const *mats, spc5_batch **out);
 void spc5_batch_free(spc5_batch *B);
+
+/* Per-matrix schedule of the batches built afterwards (the paper notes that
+ * the best kernel settings depend on the matrix, Section 2.2): the cap, in
+ * panels, of one work item's tile.  Value-mode batches (every matrix
+ * beta(1,c)) cut the matrix's batch schedule into tiles of at most this many
+ * panels (besides the value and block caps); the work-queue kernel uses it as
+ * the SpMM tile width.  0 (the default) restores the built-in choice: as many
+ * panels as a tile holds, or the matrix's sweep tile width.  1..256.  Takes
+ * effect at spc5_batch_create.  Errors: SPC5_EINVAL (NULL A, cap out of
+ * range). */
+int spc5_set_batch_schedule(spc5_matrix *A, int panels_per_tile);
 
 /* Bind the operands: X[m], Y[m] are host arrays of nmat device pointers,
  * laid out as in spc5_spmm, with the same nrhs (1..64) for every matrix.  The

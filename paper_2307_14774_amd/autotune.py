@@ -7,8 +7,11 @@ model ranks the candidate shapes by the algorithmic bytes of one product,
     bytes(r,c) = vb*nnz + 4*nblocks + r*ceil(c/8)*nblocks + 4*(npanels+1)
                  + vb*(ncols + nrows)*k,
 with nblocks counted on the device for every candidate (spc5_plan).
-Schedule: optionally measured -- the batched/SpMM tile width (panels per
-wavefront) is timed around the model's default and the fastest kept.
+Schedule: measured -- for a single matrix's SpMM, the tile width (panels per
+wavefront) is timed around the model's default and the fastest kept; for a
+batch, each matrix's batch tile cap (spc5_set_batch_schedule) is timed on a
+batch of that matrix alone with the batch's number of right-hand sides, and
+the fastest candidate kept.
 """
 from __future__ import annotations
 
@@ -71,6 +74,47 @@ def tune_schedule(M: "spc5.Spc5Matrix", nrhs: int, repeats: int = 5) -> int:
     if kernel != "sweep":
         M.set_schedule(kernel, staged_ppt if kernel == "staged" else best)
     return best
+
+
+BATCH_PPT = (0, 128, 64, 32)    # 0: as many panels as a tile holds
+
+
+def tune_batch_schedule(M: "spc5.Spc5Matrix", nrhs: int, candidates=BATCH_PPT,
+                        repeats: int = 5) -> int:
+    """Time a batch of M alone, with nrhs right-hand sides, for every
+    candidate tile cap; keep the fastest on M (spc5_set_batch_schedule) and
+    return it."""
+    import torch
+    inf = M.info
+    dev = torch.device("cuda")
+    X = torch.zeros((inf.ncols, nrhs), dtype=M.torch_dtype, device=dev)
+    Y = torch.empty((inf.nrows, nrhs), dtype=M.torch_dtype, device=dev)
+    best, best_t = 0, None
+    for ppt in candidates:
+        M.set_batch_schedule(ppt)
+        B = spc5.Spc5Batch([M])
+        B.set_operands([X], [Y])
+        B.run()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(repeats):
+            B.run()
+        b.record()
+        torch.cuda.synchronize()
+        t = a.elapsed_time(b)
+        B.free()
+        if best_t is None or t < best_t:
+            best, best_t = ppt, t
+    M.set_batch_schedule(best)
+    return best
+
+
+def tune_batch(mats, nrhs: int, candidates=BATCH_PPT) -> list:
+    """tune_batch_schedule for every matrix of a batch (before
+    spc5_batch_create); returns the chosen caps."""
+    return [tune_batch_schedule(M, nrhs, candidates) for M in mats]
 
 
 def autotune(A, dtype: str = "float64", nrhs: int = 1, measure: bool = False):

@@ -493,8 +493,10 @@ int spc5_spmv_transpose_values(const spc5_matrix *A, const void *values, const v
 
 int spc5_set_variant(spc5_matrix *A, int flags) {
     if (!A) return fail(SPC5_EINVAL, "A is NULL");
-    if (flags < 0 || flags > (SPC5_VARIANT_PARTIAL_X | SPC5_VARIANT_ROW_REDUCE))
-        return fail(SPC5_EINVAL, "unknown variant flags %d", flags);
+    const bool known = flags >= 0 && flags <= (SPC5_VARIANT_PARTIAL_X | SPC5_VARIANT_ROW_REDUCE);
+    if (!known && flags != SPC5_VARIANT_UNION_X)
+        return fail(SPC5_EINVAL, "unknown variant flags %d (union-x load combines with none)",
+                    flags);
     if (flags != 0) {
         if (A->kernel != SPC5_KERNEL_STAGED)
             return fail(SPC5_EUNSUPPORTED, "variants apply to the staged kernel only");

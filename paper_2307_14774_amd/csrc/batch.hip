@@ -218,19 +218,23 @@ __device__ __forceinline__ TileBounds item_bounds(const BatchDescV &d, int64_t t
 }
 
 // Persistent value-mode batch.  Workgroups take chunks of kGrab consecutive
-// (matrix, tile, chunk of KC right-hand sides) items from a device counter
-// until the list is exhausted; inside a chunk the next item is staged while
-// the current one is computed, as in the single-matrix value-mode kernel.
-// Per item: block popcount scan, column decode, then for one right-hand side
-// one x load per value slot (all in flight together) and in-place products
-// summed per row; for KC right-hand sides each row walks its values with
-// KC-wide x loads.  A butterfly over the S sub-lanes of a row, one store.
+// (matrix, tile) items from a device counter until the list is exhausted;
+// inside a chunk the next item is staged while the current one is computed,
+// as in the single-matrix value-mode kernel.  Per item: block popcount scan,
+// column decode, then for one right-hand side one x load per value slot (all
+// in flight together) and in-place products summed per row; for several
+// right-hand sides the tile stays in LDS (the matrix is streamed once) while
+// each chunk of KC of them is summed, each value slot loading the chunk's KC
+// entries of its X row together (for KC = 16 in FP64, one 128-byte line).  A
+// butterfly over the S sub-lanes of a row, one store.
 constexpr int kGrab = 4;
 
 // FP32 tiles leave LDS for 6 resident workgroups per compute unit; the
-// register budget is set to match.
+// register budget is set to match (not for 16 right-hand sides at once, whose
+// accumulators would then spill).
 template <typename T, int KC>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1)))
+__global__ __launch_bounds__(kWG)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && KC < 16 ? 6 : 1)))
 void k_batch_v(const BatchDescV *__restrict__ descs, const int32_t *__restrict__ work,
                int64_t nwork, unsigned *counter, int nch, int ld, T *__restrict__ partial) {
     __shared__ VTileLds<T> L;
@@ -253,18 +257,17 @@ void k_batch_v(const BatchDescV *__restrict__ descs, const int32_t *__restrict__
 
         BatchDescV d = descs[work[wbase]];
         int64_t local = wbase - d.w0;
-        TileBounds b = item_bounds(d, local / nch);
+        TileBounds b = item_bounds(d, local);
         int mb = d.cclass > 8 ? 2 : 1;
         BStage<T> st;
         st.issue(d, b, mb);
 
         for (int64_t w = wbase; w < wend; ++w) {
-            const int t0 = (int)(local % nch) * KC;
             // the next item (the current one again past the chunk's end)
             const int64_t wn = w + 1 < wend ? w + 1 : w;
             const BatchDescV dn = descs[work[wn]];
             const int64_t localn = wn - dn.w0;
-            const TileBounds bn = item_bounds(dn, localn / nch);
+            const TileBounds bn = item_bounds(dn, localn);
             const int mbn = dn.cclass > 8 ? 2 : 1;
 
             __syncthreads();
@@ -322,49 +325,72 @@ void k_batch_v(const BatchDescV *__restrict__ descs, const int32_t *__restrict__
                 vs = L.boff[max(sbp[pl], b.b0) - b.b0];
                 ve = L.boff[min(sbp[pl + 1], b.b1) - b.b0];
             };
-            auto emit = [&](int pl, const T *acc) {
-                const int64_t row = (int64_t)(b.p0 + pl);
-#pragma unroll
-                for (int q = 0; q < KC; ++q) {
-                    if (b.f) partial[w * KC + q] = acc[q];    // summed by k_batch_fix
-                    else if (row < d.nrows) ((T *)d.Y)[row * ld + t0 + q] = acc[q];
-                }
-            };
+            // one right-hand side: one x load per value slot (all in flight
+            // together), then the next item's staging, then the products in
+            // place and the row sums
+            bool done = false;
             if constexpr (KC == 1) {
-                // one x load per value slot, then the next item's staging
-                T xg[NX];
+                if (nch == 1) {
+                    T xg[NX];
 #pragma unroll
-                for (int k = 0; k < NX; ++k) {
-                    const int v = th + kWG * k;
-                    xg[k] = buf_load<T>(xb, v < nv ? (uint32_t)((int64_t)L.vcol[v] * ld + t0) *
-                                                         (uint32_t)sizeof(T)
-                                                   : kOOB);
+                    for (int k = 0; k < NX; ++k) {
+                        const int v = th + kWG * k;
+                        xg[k] = buf_load<T>(xb, v < nv ? (uint32_t)L.vcol[v] * (uint32_t)sizeof(T)
+                                                       : kOOB);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    st.issue(dn, bn, mbn);
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int k = 0; k < NX; ++k) {
+                        const int v = th + kWG * k;
+                        if (v < nv) sval[v] = sval[v] * xg[k];
+                    }
+                    __syncthreads();
+                    value_rows<T, 1>(
+                        np, range, [&](int v, T *acc) { acc[0] += sval[v]; },
+                        [&](int pl, const T *acc) {
+                            const int64_t row = (int64_t)(b.p0 + pl);
+                            if (b.f) partial[w] = acc[0];    // summed by k_batch_fix
+                            else if (row < d.nrows) ((T *)d.Y)[row] = acc[0];
+                        },
+                        L.longrow, &L.nlong);
+                    done = true;
                 }
+            }
+            if (!done) {
+                // several right-hand sides: the tile stays in LDS while each
+                // chunk of KC of them is summed, every value slot loading the
+                // chunk's KC entries of its X row at once
                 __builtin_amdgcn_sched_barrier(0);
                 st.issue(dn, bn, mbn);
                 __builtin_amdgcn_sched_barrier(0);
+                for (int ch = 0; ch < nch; ++ch) {
+                    const int t0 = ch * KC;
+                    if (ch > 0) {
+                        __syncthreads();    // every thread has read nlong
+                        if (th == 0) L.nlong = 0;
+                        __syncthreads();
+                    }
+                    value_rows<T, KC>(
+                        np, range,
+                        [&](int v, T *acc) {
+                            T xa[KC];
+                            load_xrow<T, KC>(xb, L.vcol[v], ld, t0, xa);
+                            const T a = sval[v];
 #pragma unroll
-                for (int k = 0; k < NX; ++k) {
-                    const int v = th + kWG * k;
-                    if (v < nv) sval[v] = sval[v] * xg[k];
+                            for (int q = 0; q < KC; ++q) acc[q] = fma(a, xa[q], acc[q]);
+                        },
+                        [&](int pl, const T *acc) {
+                            const int64_t row = (int64_t)(b.p0 + pl);
+#pragma unroll
+                            for (int q = 0; q < KC; ++q) {
+                                if (b.f) partial[w * ld + t0 + q] = acc[q];    // k_batch_fix
+                                else if (row < d.nrows) ((T *)d.Y)[row * ld + t0 + q] = acc[q];
+                            }
+                        },
+                        L.longrow, &L.nlong);
                 }
-                __syncthreads();
-                value_rows<T, 1>(np, range, [&](int v, T *acc) { acc[0] += sval[v]; }, emit,
-                                 L.longrow, &L.nlong);
-            } else {
-                __builtin_amdgcn_sched_barrier(0);
-                st.issue(dn, bn, mbn);
-                __builtin_amdgcn_sched_barrier(0);
-                value_rows<T, KC>(
-                    np, range,
-                    [&](int v, T *acc) {
-                        T xa[KC];
-                        load_xrow<T, KC>(xb, L.vcol[v], ld, t0, xa);
-                        const T a = sval[v];
-#pragma unroll
-                        for (int q = 0; q < KC; ++q) acc[q] = fma(a, xa[q], acc[q]);
-                    },
-                    emit, L.longrow, &L.nlong);
             }
             d = dn;
             local = localn;
@@ -387,7 +413,7 @@ __global__ void k_batch_fix(const BatchFix *__restrict__ fix, int64_t nfix,
     const int ch = rhs / KC, q = rhs % KC;
     const BatchDescV &d = descs[fx.mat];
     T acc = T(0);
-    for (int64_t t = fx.t0; t <= fx.t1; ++t) acc += partial[(d.w0 + t * nch + ch) * KC + q];
+    for (int64_t t = fx.t0; t <= fx.t1; ++t) acc += partial[(d.w0 + t) * ld + ch * KC + q];
     ((T *)d.Y)[(int64_t)fx.row * ld + rhs] = acc;
 }
 
@@ -413,28 +439,26 @@ static int batch_grid_v() {
     return blocks * prop.multiProcessorCount;
 }
 
-template <typename T>
-static hipError_t launch_batch_v(const spc5_batch *B, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, B->d_counter);
+template <typename T, int KC>
+static void launch_batch_vk(const spc5_batch *B, hipStream_t s) {
     const BatchDescV *d = (const BatchDescV *)B->d_desc;
-    if (B->kchunk == 4)
-        hipLaunchKernelGGL((k_batch_v<T, 4>), dim3(B->grid), dim3(kWG), 0, s, d, B->d_work,
-                           B->nwork, B->d_counter, B->nch, B->nrhs, (T *)B->d_partial);
-    else
-        hipLaunchKernelGGL((k_batch_v<T, 1>), dim3(B->grid), dim3(kWG), 0, s, d, B->d_work,
-                           B->nwork, B->d_counter, B->nch, B->nrhs, (T *)B->d_partial);
+    hipLaunchKernelGGL((k_batch_v<T, KC>), dim3(B->grid), dim3(kWG), 0, s, d, B->d_work,
+                       B->nwork, B->d_counter, B->nch, B->nrhs, (T *)B->d_partial);
     if (B->nfix > 0) {
         const int64_t n = B->nfix * B->nrhs;
         const unsigned g = (unsigned)((n + 255) / 256);
-        if (B->kchunk == 4)
-            hipLaunchKernelGGL((k_batch_fix<T, 4>), dim3(g), dim3(256), 0, s,
-                               (const BatchFix *)B->d_fix, B->nfix, d, B->nch, B->nrhs,
-                               (const T *)B->d_partial);
-        else
-            hipLaunchKernelGGL((k_batch_fix<T, 1>), dim3(g), dim3(256), 0, s,
-                               (const BatchFix *)B->d_fix, B->nfix, d, B->nch, B->nrhs,
-                               (const T *)B->d_partial);
+        hipLaunchKernelGGL((k_batch_fix<T, KC>), dim3(g), dim3(256), 0, s,
+                           (const BatchFix *)B->d_fix, B->nfix, d, B->nch, B->nrhs,
+                           (const T *)B->d_partial);
     }
+}
+
+template <typename T>
+static hipError_t launch_batch_v(const spc5_batch *B, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, s, B->d_counter);
+    if (B->kchunk == 16) launch_batch_vk<T, 16>(B, s);
+    else if (B->kchunk == 4) launch_batch_vk<T, 4>(B, s);
+    else launch_batch_vk<T, 1>(B, s);
     return hipGetLastError();
 }
 
@@ -477,11 +501,12 @@ int count_blocks_device(const int64_t *d_rowptr, const int32_t *d_colidx, int64_
                         int c, int64_t *nblocks);
 
 // Value-mode binding: every matrix is beta(1,c) with a staged schedule.
-// Work items are (matrix, staged tile, chunk of KC right-hand sides); the
-// split panels of all matrices form the fixup list.
+// Work items are (matrix, staged tile) pairs, each for all right-hand sides
+// (chunks of KC = 16, 4 or 1 of them); the split panels of all matrices form
+// the fixup list.
 template <typename T>
 static int bind_value_mode(spc5_batch *B, int nrhs, const void *const *X, void *const *Y) {
-    const int KC = nrhs % 4 == 0 ? 4 : 1;
+    const int KC = nrhs % 16 == 0 ? 16 : (nrhs % 4 == 0 ? 4 : 1);
     const int nch = nrhs / KC;
     std::vector<BatchDescV> desc(B->nmat);
     std::vector<int32_t> work;
@@ -507,7 +532,7 @@ static int bind_value_mode(spc5_batch *B, int nrhs, const void *const *X, void *
         d.w0 = w0;
         d.cclass = A->c <= 4 ? 4 : (A->c <= 8 ? 8 : 16);
         d.pad = 0;
-        const int64_t items = Sd->ntiles_staged * nch;
+        const int64_t items = Sd->ntiles_staged;
         if (w0 + items >= ((int64_t)1 << 31)) return fail(SPC5_EUNSUPPORTED, "too many tiles");
         work.insert(work.end(), (size_t)items, (int32_t)m);
         if (Sd->nsplit > 0) {
@@ -530,7 +555,7 @@ static int bind_value_mode(spc5_batch *B, int nrhs, const void *const *X, void *
         (e = hipMalloc((void **)&B->d_work, std::max<size_t>(4, nw * 4))) != hipSuccess ||
         (!fix.empty() &&
          ((e = hipMalloc(&B->d_fix, sizeof(BatchFix) * fix.size())) != hipSuccess ||
-          (e = hipMalloc(&B->d_partial, nw * (size_t)KC * sizeof(T))) != hipSuccess)) ||
+          (e = hipMalloc(&B->d_partial, nw * (size_t)nrhs * sizeof(T))) != hipSuccess)) ||
         (e = hipMemcpy(B->d_desc, desc.data(), sizeof(BatchDescV) * desc.size(),
                        hipMemcpyHostToDevice)) != hipSuccess ||
         (nw > 0 && (e = hipMemcpy(B->d_work, work.data(), nw * 4, hipMemcpyHostToDevice)) !=
@@ -546,7 +571,8 @@ static int bind_value_mode(spc5_batch *B, int nrhs, const void *const *X, void *
     B->nch = nch;
     B->nwork = (int64_t)nw;
     B->nfix = (int64_t)fix.size();
-    B->grid = KC == 4 ? batch_grid_v<T, 4>() : batch_grid_v<T, 1>();
+    B->grid = KC == 16 ? batch_grid_v<T, 16>() : KC == 4 ? batch_grid_v<T, 4>()
+                                                         : batch_grid_v<T, 1>();
     B->grid = (int)std::max<int64_t>(1, std::min<int64_t>(B->grid, B->nwork));
     return SPC5_OK;
 }
@@ -594,7 +620,7 @@ int spc5_batch_create(int nmat, spc5_matrix *const *mats, spc5_batch **out) {
             S.r = A->r; S.c = A->c; S.dtype = A->dtype; S.mask_bytes = A->mask_bytes;
             S.device = A->device;
             S.blk_ptr = A->blk_ptr; S.masks = A->masks; S.panel_val = A->panel_val;
-            const int st = build_staged_schedule(&S, 0, false);
+            const int st = build_staged_schedule(&S, A->batch_ppt, false);
             S.blk_ptr = nullptr; S.masks = nullptr; S.panel_val = nullptr;
             if (st != SPC5_OK) {
                 spc5_batch_free(B);
@@ -617,6 +643,14 @@ void spc5_batch_free(spc5_batch *B) {
     for (spc5_matrix &S : B->sched) free_staged_schedule(&S);
     if (B->d_counter) (void)hipFree(B->d_counter);
     delete B;
+}
+
+int spc5_set_batch_schedule(spc5_matrix *A, int panels_per_tile) {
+    if (!A) return fail(SPC5_EINVAL, "A is NULL");
+    if (panels_per_tile < 0 || panels_per_tile > 256)
+        return fail(SPC5_EINVAL, "panels_per_tile must be in 0..256");
+    A->batch_ppt = panels_per_tile;
+    return SPC5_OK;
 }
 
 int spc5_batch_set_operands(spc5_batch *B, int nrhs, const void *const *X, void *const *Y) {
@@ -654,7 +688,8 @@ int spc5_batch_set_operands(spc5_batch *B, int nrhs, const void *const *X, void 
         d.npanels = A->npanels;
         d.nrows = A->nrows;
         d.shape = A->r * 100 + (A->c <= 4 ? 4 : (A->c <= 8 ? 8 : 16));
-        d.ppt = std::max(1, std::min(A->ppt, kSpmmTile / (A->r * K)));
+        const int want = A->batch_ppt ? A->batch_ppt : A->ppt;
+        d.ppt = std::max(1, std::min(want, kSpmmTile / (A->r * K)));
         d.tile0 = tile0;
         const int64_t nt = (A->npanels + d.ppt - 1) / d.ppt;
         if (tile0 + nt >= ((int64_t)1 << 31)) return fail(SPC5_EUNSUPPORTED, "too many tiles");

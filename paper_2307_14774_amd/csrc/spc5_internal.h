@@ -18,6 +18,7 @@ struct spc5_matrix {
     int mask_bytes = 1;
     int ppt = 1;           // panels per wavefront tile (sweep kernel)
     int sppt = 1;          // panels per wavefront tile (staged kernel)
+    int batch_ppt = 0;     // tile cap in panels for batches (spc5_set_batch_schedule; 0: default)
     bool hot_cols = false; // some column holds thousands of entries (sampled at conversion)
     int kernel = SPC5_KERNEL_ROWS;   // forward kernel in use (never AUTO)
     int64_t max_panel_blocks = 0;

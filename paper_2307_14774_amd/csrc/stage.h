@@ -48,6 +48,7 @@ void staged_caps(const spc5_matrix *A, int *vt, int *bt, int *ppw);
 // Kernel variants for the paper's ablations (spc5_set_variant).
 constexpr int kVarPartialX = 1;    // each row loads its own x (Section 3.1)
 constexpr int kVarRowReduce = 2;   // per-row sums of the sub-lanes (Section 3.2)
+constexpr int kVarUnionX = 4;      // window pieces the union of the row masks uses (3.1)
 
 // C consecutive entries of x from byte offset off (kOOB: none) as 16-byte
 // raw buffer loads; entries past the descriptor's range read as zero (the
@@ -59,6 +60,35 @@ __device__ __forceinline__ void load_window(const Buf &xb, uint32_t off, T *out)
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
         const v4u v = buf_load16(xb, off + 16u * q);
+        if constexpr (sizeof(T) == 8) {
+            typedef double v2d __attribute__((ext_vector_type(2)));
+            const v2d f = __builtin_bit_cast(v2d, v);
+            out[2 * q] = f.x;
+            out[2 * q + 1] = f.y;
+        } else {
+            typedef float v4f __attribute__((ext_vector_type(4)));
+            const v4f f = __builtin_bit_cast(v4f, v);
+            out[4 * q] = f.x;
+            out[4 * q + 1] = f.y;
+            out[4 * q + 2] = f.z;
+            out[4 * q + 3] = f.w;
+        }
+    }
+}
+
+// The same window, but only the 16-byte pieces that hold a column of `un`
+// (the union of the block's row masks): a piece no row uses is not loaded
+// and reads as zero.
+template <typename T, int C>
+__device__ __forceinline__ void load_window_union(const Buf &xb, uint32_t off, unsigned un,
+                                                  T *out) {
+    constexpr int NV = C * (int)sizeof(T) / 16;
+    constexpr int PER = 16 / (int)sizeof(T);            // columns per piece
+    static_assert(NV >= 1, "window narrower than one 16-byte load");
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const unsigned pm = ((1u << PER) - 1u) << (q * PER);
+        const v4u v = buf_load16(xb, (un & pm) ? off + 16u * q : kOOB);
         if constexpr (sizeof(T) == 8) {
             typedef double v2d __attribute__((ext_vector_type(2)));
             const v2d f = __builtin_bit_cast(v2d, v);

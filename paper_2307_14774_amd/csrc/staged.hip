@@ -267,6 +267,10 @@ __attribute__((amdgpu_waves_per_eu(stream_residency<T, R, C, NVG, VAR>()))) void
         if constexpr (VAR & kVarPartialX) {
 #pragma unroll
             for (int k = 0; k < C; ++k) xw[k] = T(0);   // rows load their own x
+        } else if constexpr (VAR & kVarUnionX) {
+            // merged predicate: only the pieces some row of the block uses
+            load_window_union<T, C>(xbuf, un ? (uint32_t)col0 * (uint32_t)sizeof(T) : kOOB, un,
+                                    xw);
         } else {
             load_window<T, C>(xbuf, un ? (uint32_t)col0 * (uint32_t)sizeof(T) : kOOB, xw);
         }
@@ -835,9 +839,14 @@ static hipError_t launch_stream(const spc5_matrix *A, const T *val, const T *x, 
                 case kVarRowReduce:
                     return launch_stream_g<T, R, C, 4, false, kVarRowReduce>(A, val, x, y, s,
                                                                             remap, partial);
-                default:
+                case kVarUnionX:
+                    return launch_stream_g<T, R, C, 4, false, kVarUnionX>(A, val, x, y, s,
+                                                                          remap, partial);
+                case kVarPartialX | kVarRowReduce:
                     return launch_stream_g<T, R, C, 4, false, kVarPartialX | kVarRowReduce>(
                         A, val, x, y, s, remap, partial);
+                default:
+                    return hipErrorInvalidValue;
             }
         }
         return hipErrorInvalidValue;

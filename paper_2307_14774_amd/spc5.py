@@ -27,6 +27,7 @@ EXPORTS = [
     "spc5_set_variant",
     "spc5_spmv", "spc5_spmv_values", "spc5_spmv_transpose", "spc5_spmv_transpose_values",
     "spc5_prepare_transpose", "spc5_values_grad", "spc5_spmm", "spc5_batch_create", "spc5_batch_free",
+    "spc5_set_batch_schedule",
     "spc5_batch_set_operands", "spc5_batch_run", "spc5_batch_spmm", "spc5_plan",
     "spc5_csr_create", "spc5_csr_free", "spc5_csr_spmv",
     "spc5_csr_bytes", "spc5_last_error", "spc5_version",
@@ -81,6 +82,7 @@ def lib():
         L.spc5_prepare_transpose.argtypes = [P, I, I]
         L.spc5_spmm.argtypes = [P, I, P, P, P]
         L.spc5_batch_create.argtypes = [I, P, ctypes.POINTER(P)]
+        L.spc5_set_batch_schedule.argtypes = [P, I]
         L.spc5_batch_free.argtypes = [P]
         L.spc5_batch_free.restype = None
         L.spc5_batch_spmm.argtypes = [P, I, P, P, P]
@@ -203,10 +205,18 @@ class Spc5Matrix:
         _check(lib().spc5_set_schedule(self._h, code, panels_per_tile))
         self.info = self._info()
 
-    def set_variant(self, partial_x: bool = False, row_reduce: bool = False):
+    def set_batch_schedule(self, panels_per_tile: int = 0):
+        """Tile cap (panels) this matrix gets in batches built afterwards;
+        0 restores the default."""
+        _check(lib().spc5_set_batch_schedule(self._h, panels_per_tile))
+
+    def set_variant(self, partial_x: bool = False, row_reduce: bool = False,
+                    union_x: bool = False):
         """Ablation variants of the staged kernel (partial x load, per-row
-        reduction); both False restores the default."""
-        _check(lib().spc5_set_variant(self._h, (1 if partial_x else 0) | (2 if row_reduce else 0)))
+        reduction, x load by the merged row predicates); all False restores
+        the default."""
+        flags = (1 if partial_x else 0) | (2 if row_reduce else 0) | (4 if union_x else 0)
+        _check(lib().spc5_set_variant(self._h, flags))
         self.info = self._info()
 
     @property

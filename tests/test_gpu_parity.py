@@ -412,23 +412,32 @@ def test_split_transpose_plan_zipf(dev):
 
 @pytest.mark.parametrize("A", [CASES[-6], CASES[-5], CASES[-2]], ids=lambda a: a.name)
 @pytest.mark.parametrize("rc", [(2, 4), (4, 4), (4, 8), (8, 8), (2, 3)], ids=lambda t: "b%d_%d" % t)
-@pytest.mark.parametrize("variant", [(True, False), (False, True), (True, True)],
-                         ids=["partial_x", "row_reduce", "both"])
+@pytest.mark.parametrize("variant", [(True, False, False), (False, True, False),
+                                     (True, True, False), (False, False, True)],
+                         ids=["partial_x", "row_reduce", "both", "union_x"])
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
 def test_staged_variants(A, rc, variant, dtype, dev):
-    """The ablation variants (partial x load, per-row reduction) compute the
-    same product: against the oracle and reproducible."""
+    """The ablation variants (partial x load, per-row reduction, x load by the
+    merged row predicates) compute the same product: against the oracle and
+    reproducible.  The union-x load changes no summation order of the rows
+    loop it runs (the branch-free one), so where the default takes that loop
+    too it equals the default bit for bit."""
     r, c = rc
     S = spc5()
     say(f"variant {variant} {A.name} beta{rc} {dtype}")
     M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c, dtype)
     M.set_schedule("staged")
-    M.set_variant(*variant)
-    assert M.info.variant == (1 if variant[0] else 0) | (2 if variant[1] else 0)
     tdt = torch.float64 if dtype == "float64" else torch.float32
     x = to_dev(A.x, dev, tdt)
+    y_default = M.spmv(x).cpu().numpy()
+    M.set_variant(*variant)
+    assert M.info.variant == ((1 if variant[0] else 0) | (2 if variant[1] else 0)
+                              | (4 if variant[2] else 0))
     y = M.spmv(x).cpu().numpy()
     assert np.array_equal(M.spmv(x).cpu().numpy(), y)
+    dense_default = 2 * A.nnz >= M.info.nblocks * r * c    # the default's rows loop
+    if variant[2] and dense_default:
+        assert np.array_equal(y, y_default)
     if dtype == "float64":
         ref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
         assert oracle.rel_l2(y, ref) <= 1e-14
@@ -453,6 +462,8 @@ def test_variant_errors(dev):
         M.set_variant(row_reduce=True)
     assert ei.value.status == -5
     assert S.lib().spc5_set_variant(M.handle, 7) == -1
+    assert S.lib().spc5_set_variant(M.handle, 5) == -1
+    assert S.lib().spc5_set_variant(M.handle, 8) == -1
 
 
 # ------------------------------------------------------------ backward
