@@ -201,6 +201,22 @@ int spc5_set_variant(spc5_matrix *A, int flags);
  * SPC5_EDEVICE. */
 int spc5_spmv(const spc5_matrix *A, const void *x, void *y, void *stream);
 
+/* y = A x like spc5_spmv, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): this call never allocates or frees.  The partial row sums of
+ * panels cut into pieces (spc5_info.split_panels > 0) go to a fixed device
+ * array of the library, SPC5_NOALLOC_SCRATCH_BYTES bytes, of which each GPU
+ * holds its own copy until the process ends.  Every call on one GPU shares
+ * that GPU's array, whatever the handle: calls that overlap in time on one
+ * GPU (several streams, or several host threads) race when their matrices
+ * have pieces.  Each call writes the partial sums it reads, so nothing
+ * carries over between calls.  Matrices without pieces use no scratch.
+ * Errors: as spc5_spmv, plus SPC5_EUNSUPPORTED when the pieces need more
+ * than SPC5_NOALLOC_SCRATCH_BYTES (npieces * r * value bytes) or the device
+ * index is 64 or more. */
+#define SPC5_NOALLOC_SCRATCH_BYTES (1 << 20)
+int spc5_spmv_noalloc(const spc5_matrix *A, const void *x, void *y, void *stream);
+
 /* Same product with the packed values taken from `values` (device,
  * nnz entries, the packed order of spc5_export) instead of the matrix's own:
  * y = A(theta) x, used by the differentiable path. */

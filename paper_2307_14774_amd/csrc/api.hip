@@ -231,6 +231,33 @@ void free_matrix(spc5_matrix *A) {
     delete A;
 }
 
+// Scratch of the allocation-free forward product: a fixed device array (one
+// copy per GPU, held until the process ends).  In host code `scratch` names
+// a host-side stand-in, never the device memory: kernels get the address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[SPC5_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::once_flag g_scratch_once[kMaxDevices];
+static void *g_scratch_ptr[kMaxDevices];
+static hipError_t g_scratch_err[kMaxDevices];
+
+// Device address of `scratch` on `dev`, looked up once per device with that
+// device current (the caller has made it current).
+static int static_scratch(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(SPC5_EUNSUPPORTED, "device %d: the fixed scratch covers devices 0..%d", dev,
+                    kMaxDevices - 1);
+    std::call_once(g_scratch_once[dev], [dev]() {
+        void *ptr = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? ptr : nullptr;
+    });
+    if (g_scratch_err[dev] != hipSuccess) return hip_fail(g_scratch_err[dev], "hipGetSymbolAddress");
+    *out = g_scratch_ptr[dev];
+    return SPC5_OK;
+}
+
 }  // namespace spc5
 
 using namespace spc5;
@@ -470,6 +497,25 @@ int spc5_spmv_values(const spc5_matrix *A, const void *values, const void *x, vo
     hipError_t e = launch_spmv(A, values ? values : A->val, x, y, (hipStream_t)stream,
                                sc.partial);
     return e == hipSuccess ? SPC5_OK : hip_fail(e, "spc5_spmv_values launch");
+}
+
+int spc5_spmv_noalloc(const spc5_matrix *A, const void *x, void *y, void *stream) {
+    int st = compute_guard(A, {{x, A ? A->ncols : 0}, {y, A ? A->nrows : 0}});
+    if (st) return st;
+    DeviceGuard g(A->device);
+    if (!g.ok) return fail(SPC5_EDEVICE, "cannot select the matrix's device");
+    void *partial = nullptr;
+    if (A->kernel == SPC5_KERNEL_STAGED && A->npieces > 0) {
+        const int64_t need = A->npieces * A->r * (A->dtype == SPC5_F64 ? 8 : 4);
+        if (need > SPC5_NOALLOC_SCRATCH_BYTES)
+            return fail(SPC5_EUNSUPPORTED,
+                        "the piece tiles' partial sums need %lld bytes, above the fixed "
+                        "scratch of %d bytes",
+                        (long long)need, SPC5_NOALLOC_SCRATCH_BYTES);
+        if ((st = static_scratch(A->device, &partial)) != SPC5_OK) return st;
+    }
+    hipError_t e = launch_spmv(A, nullptr, x, y, (hipStream_t)stream, partial);
+    return e == hipSuccess ? SPC5_OK : hip_fail(e, "spc5_spmv_noalloc launch");
 }
 
 int spc5_spmv_transpose(const spc5_matrix *A, const void *ybar, void *xbar, void *stream) {

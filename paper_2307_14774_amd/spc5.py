@@ -25,7 +25,8 @@ EXPORTS = [
     "csr_to_spc5", "spc5_free", "spc5_get_info", "spc5_export", "spc5_to_csr",
     "spc5_set_schedule",
     "spc5_set_variant",
-    "spc5_spmv", "spc5_spmv_values", "spc5_spmv_transpose", "spc5_spmv_transpose_values",
+    "spc5_spmv", "spc5_spmv_noalloc", "spc5_spmv_values", "spc5_spmv_transpose",
+    "spc5_spmv_transpose_values",
     "spc5_prepare_transpose", "spc5_values_grad", "spc5_spmm", "spc5_batch_create", "spc5_batch_free",
     "spc5_set_batch_schedule",
     "spc5_batch_set_operands", "spc5_batch_run", "spc5_batch_spmm", "spc5_plan",
@@ -76,6 +77,7 @@ def lib():
         L.spc5_set_variant.argtypes = [P, I]
         L.spc5_spmv.argtypes = [P, P, P, P]
         L.spc5_spmv_values.argtypes = [P, P, P, P, P]
+        L.spc5_spmv_noalloc.argtypes = [P, P, P, P]
         L.spc5_spmv_transpose.argtypes = [P, P, P, P]
         L.spc5_spmv_transpose_values.argtypes = [P, P, P, P, P]
         L.spc5_values_grad.argtypes = [P, P, P, P, P]
@@ -252,6 +254,14 @@ class Spc5Matrix:
             y = torch.empty(inf.nrows, dtype=self.torch_dtype, device=x.device)
         _check(lib().spc5_spmv(self._h, _dev_ptr(x, inf.dtype, inf.ncols, "x"),
                                _dev_ptr(y, inf.dtype, inf.nrows, "y"), _stream(stream)))
+        return y
+
+    def spmv_noalloc(self, x, y, stream=None):
+        """y = A x through the allocation-free entry point (piece-tile partial
+        sums in the library's fixed device array); y must be given."""
+        inf = self.info
+        _check(lib().spc5_spmv_noalloc(self._h, _dev_ptr(x, inf.dtype, inf.ncols, "x"),
+                                       _dev_ptr(y, inf.dtype, inf.nrows, "y"), _stream(stream)))
         return y
 
     def spmv_values(self, values, x, y=None, stream=None):

@@ -79,6 +79,7 @@ def test_null_out_and_null_handles():
     st, _ = _create([0, 1], [0], [1.0], 1, 3, out=False)
     assert st == -1
     assert L.spc5_spmv(None, None, None, None) == -1
+    assert L.spc5_spmv_noalloc(None, None, None, None) == -1
     assert L.spc5_spmv_transpose(None, None, None, None) == -1
     assert L.spc5_get_info(None, None) == -1
     assert L.spc5_to_csr(None, None, None, None) == -1
