@@ -233,24 +233,28 @@ int spc5_spmv_values(const spc5_matrix *A, const void *values, const void *x,
  * column holds thousands of entries (sampled at conversion) the
  * contributions are first summed per workgroup in LDS, so a popular column
  * takes one atomic per workgroup rather than one per row.
- * With a plan (spc5_prepare_transpose): the forward kernel over the stored
- * A^T; no atomics, the result is reproducible bit for bit.  When `values` is
- * given, the plan first moves them to A^T's order (two passes through the
- * calling stream's scratch, two value arrays of nnz entries: a scatter into
- * staging slots grouped by position in A^T, then a gather inside each
- * group). */
+ * With a plan (spc5_prepare_transpose) there are no atomics and the result
+ * is reproducible bit for bit.  The matrix's own values: the forward kernel
+ * over the stored A^T.  Caller values: each product value * ybar[row] is
+ * formed in A's packed order and the products are summed in A^T's CSR order,
+ * in two passes through the calling stream's scratch (nnz values plus two
+ * per 16384 nonzeros): a scatter of the products into staging slots grouped
+ * by position in A^T, then per group a gather in A^T's order and segmented
+ * row sums (rows cut by a group edge are completed by a small fixup in
+ * group order). */
 int spc5_spmv_transpose(const spc5_matrix *A, const void *ybar, void *xbar,
                         void *stream);
 int spc5_spmv_transpose_values(const spc5_matrix *A, const void *values,
                                const void *ybar, void *xbar, void *stream);
 
 /* Build the transposed-product plan of A: A^T converted on the device to
- * SPC5 beta(r,c) storage (r = c = 0: A's own shape) plus the two index
- * arrays that move caller values from A's packed order to A^T's.
- * Afterwards spc5_spmv_transpose* run as a forward product over A^T.  Costs
- * about the device memory of A once more, plus 8 bytes per nonzero (the two
- * index arrays); held until spc5_free.  Each stream that calls a transpose
- * with caller values adds two value arrays of scratch.  Synchronous.
+ * SPC5 beta(r,c) storage (r = c = 0: A's own shape), for transposes with the
+ * matrix's own values, plus the tables of transposes with caller values:
+ * A's row of every packed value, the index arrays that move products from
+ * A's packed order to A^T's CSR order, and A^T's row pointer.  Costs about
+ * the device memory of A once more, plus 12 bytes per nonzero and 4 per
+ * column; held until spc5_free.  Each stream that calls a transpose with
+ * caller values adds one value array of scratch.  Synchronous.
  * Calling it again with the same shape is a no-op.
  * Errors: SPC5_EINVAL (NULL A, a plan with another shape exists),
  * SPC5_EUNSUPPORTED (r or c out of range, A^T's block count >= 2^31),

@@ -3,10 +3,12 @@
 theta holds the matrix's nonzeros in SPC5 packed order (the order of
 Spc5Matrix.export()); the sparsity pattern (anchors and masks) is fixed.
 Backward, both in HIP kernels of libspc5:
-  xbar     = A(theta)^T ybar   (spc5_spmv_transpose_values: the forward kernel
-                                over the stored A^T when the matrix has a
-                                transpose plan, else the masked scatter)
+  xbar     = A(theta)^T ybar   (spc5_spmv_transpose_values through the
+                                matrix's transpose plan: products formed in
+                                A's order, summed in A^T's order, no atomics)
   thetabar = ybar[row(v)] * x[col(v)] in packed order (spc5_values_grad)
+The forward builds the transpose plan when the matrix has none (once, before
+the first backward); the atomic scatter without a plan is never used here.
 This module only wires the calls; it computes nothing itself.
 """
 from __future__ import annotations
@@ -19,6 +21,8 @@ from .spc5 import Spc5Matrix
 class Spc5MatVec(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta: torch.Tensor, x: torch.Tensor, A: Spc5Matrix):
+        if not A.has_transpose_plan:
+            A.prepare_transpose()
         theta = theta.contiguous()
         x = x.contiguous()
         y = A.spmv_values(theta, x)

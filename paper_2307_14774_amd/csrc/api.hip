@@ -165,7 +165,7 @@ struct ScratchPool {
 void free_pool(spc5_matrix *A) {
     if (!A->pool) return;
     for (auto &sl : A->pool->slots)
-        for (void *p : {sl.sc.partial, sl.sc.tr_partial, sl.sc.stage, sl.sc.vals})
+        for (void *p : {sl.sc.partial, sl.sc.tr_partial, sl.sc.stage, sl.sc.edges})
             if (p) (void)hipFree(p);
     delete A->pool;
     A->pool = nullptr;
@@ -187,11 +187,14 @@ int pool_scratch(const spc5_matrix *A, hipStream_t s, int need, Scratch *out) {
     *out = Scratch();
     const size_t vb = A->dtype == SPC5_F64 ? 8 : 4;
     const spc5_matrix *T = A->tr;
-    size_t want[4] = {0, 0, 0, 0};    // partial, tr_partial, stage, vals
+    size_t want[4] = {0, 0, 0, 0};    // partial, tr_partial, stage, edges
     if ((need & kNeedPartial) && A->npieces > 0) want[0] = (size_t)A->npieces * A->r * vb;
     if ((need & kNeedTrPartial) && T && T->npieces > 0)
         want[1] = (size_t)T->npieces * T->r * vb;
-    if ((need & kNeedTheta) && A->nnz > 0) want[2] = want[3] = (size_t)A->nnz * vb;
+    if ((need & kNeedTheta) && A->nnz > 0) {
+        want[2] = (size_t)(A->nnz + 16) * vb;    // read 16 at a time by the bucket pass
+        want[3] = (size_t)2 * A->tr_nbuckets * vb;
+    }
     if (!want[0] && !want[1] && !want[2]) return SPC5_OK;
     if (!A->pool) return fail(SPC5_EINVAL, "handle has no scratch pool");
     std::lock_guard<std::mutex> lock(A->pool->mu);
@@ -202,7 +205,8 @@ int pool_scratch(const spc5_matrix *A, hipStream_t s, int need, Scratch *out) {
         A->pool->slots.push_back({s, Scratch()});
         slot = &A->pool->slots.back();
     }
-    void **part[4] = {&slot->sc.partial, &slot->sc.tr_partial, &slot->sc.stage, &slot->sc.vals};
+    void **part[4] = {&slot->sc.partial, &slot->sc.tr_partial, &slot->sc.stage,
+                      &slot->sc.edges};
     for (int q = 0; q < 4; ++q) {
         if (!want[q] || *part[q]) continue;
         const hipError_t e = scratch_alloc(part[q], want[q]);
@@ -220,7 +224,9 @@ void free_matrix(spc5_matrix *A) {
     DeviceGuard g(A->device);
     free_matrix(A->tr);
     free_pool(A);
-    for (void *p : {(void *)A->tr_lidx, (void *)A->tr_gpos, (void *)A->tr_src})
+    for (void *p : {(void *)A->tr_lidx, (void *)A->tr_gpos, (void *)A->tr_src,
+                    A->tr_arow, (void *)A->tr_cbase, (void *)A->tr_hoff, (void *)A->tr_hpos,
+                    (void *)A->tr_hrow, (void *)A->tr_edge_rows})
         if (p) (void)hipFree(p);
     if (A->blk_ptr) (void)hipFree(A->blk_ptr);
     if (A->blk_col) (void)hipFree(A->blk_col);
@@ -452,7 +458,9 @@ int spc5_set_schedule(spc5_matrix *A, int kernel, int ppt) {
     if (A->kernel != SPC5_KERNEL_STAGED) A->variant = 0;
     if (A->kernel == SPC5_KERNEL_STAGED) {
         DeviceGuard g(A->device);
-        return build_staged_schedule(A, ppt);
+        int st = build_staged_schedule(A, ppt);
+        if (st == SPC5_OK && A->variant != 0) st = fit_schedule_to_variants(A, true);
+        return st;
     }
     A->ppt = ppt ? ppt
                  : default_ppt(A->npanels ? (double)A->nblocks * A->r / (double)A->npanels : 0.0);
@@ -528,8 +536,8 @@ int spc5_spmv_transpose_values(const spc5_matrix *A, const void *values, const v
     if (st) return st;
     DeviceGuard g(A->device);
     Scratch sc;
-    if (A->tr && (st = pool_scratch(A, (hipStream_t)stream,
-                                    kNeedTrPartial | (values ? kNeedTheta : 0), &sc)) != SPC5_OK)
+    if (A->tr && (st = pool_scratch(A, (hipStream_t)stream, values ? kNeedTheta : kNeedTrPartial,
+                                    &sc)) != SPC5_OK)
         return st;
     hipError_t e = A->tr ? launch_transpose_plan(A, values, ybar, xbar, (hipStream_t)stream, sc)
                          : launch_transpose(A, values ? values : A->val, ybar, xbar,
@@ -548,6 +556,11 @@ int spc5_set_variant(spc5_matrix *A, int flags) {
             return fail(SPC5_EUNSUPPORTED, "variants apply to the staged kernel only");
         if (!(A->r == 2 || A->r == 4 || A->r == 8) || A->c > 8)
             return fail(SPC5_EUNSUPPORTED, "variants exist for r in {2,4,8}, c <= 8");
+    }
+    if (A->kernel == SPC5_KERNEL_STAGED && (flags != 0) != (A->variant != 0)) {
+        DeviceGuard g(A->device);
+        const int st = fit_schedule_to_variants(A, flags != 0);
+        if (st != SPC5_OK) return st;
     }
     A->variant = flags;
     return SPC5_OK;

@@ -203,6 +203,61 @@ __device__ __forceinline__ void load_xrow(const Buf &xb, int64_t row, int ld, in
     }
 }
 
+// Row sums of a value-mode tile for K right-hand sides split over G lanes
+// per row sub-lane (K/G each), for K up to 16: like value_rows, but the G
+// lanes of a sub-lane walk the same values, each loading its K/G entries of
+// the value's X row, so one wavefront load instruction covers whole X rows
+// of several values instead of one entry group of many; the accumulators per
+// lane stay at K/G.  Rows are summed in a fixed order (reproducible).
+// term(v, g, acc) adds value slot v for lane group g into acc[0..K/G);
+// emit(row, g, acc) stores.  *s_nlong must be zero at entry.
+template <typename T, int KG, int G, typename Range, typename Term, typename Emit>
+__device__ __forceinline__ void value_rows_g(int np, Range range, Term term, Emit emit,
+                                             int *s_long, int *s_nlong) {
+    const int th = threadIdx.x, lane = lane_id(), wv = th / kWave;
+    int lgS = 0;
+    while (np * (2 << lgS) * G <= kWG && (2 << lgS) * G <= kWave) ++lgS;
+    const int S = 1 << lgS;
+    // rows in rounds of kWG / (S*G): a tile may hold more rows than the
+    // workgroup has lane groups
+    const int per_round = kWG / (S * G);
+    const int sub = (th / G) & (S - 1), g = th % G;
+    for (int base = 0; base < np; base += per_round) {
+        const int pl = base + th / (S * G);
+        const bool live = pl < np;
+        int vs = 0, ve = 0;
+        if (live) range(pl, vs, ve);
+        const bool lng = live && ve - vs > S * kShortRow;
+        T acc[KG];
+#pragma unroll
+        for (int q = 0; q < KG; ++q) acc[q] = T(0);
+        if (live && !lng)
+            for (int v = vs + sub; v < ve; v += S) term(v, g, acc);
+        if (lng && sub == 0 && g == 0) s_long[atomicAdd(s_nlong, 1)] = pl;
+#pragma unroll
+        for (int q = 0; q < KG; ++q)
+            for (int d = G; d < S * G; d <<= 1) acc[q] += __shfl_xor(acc[q], d);
+        if (live && !lng && sub == 0) emit(pl, g, acc);
+    }
+    __syncthreads();
+    const int nl = *s_nlong;
+    constexpr int WS = kWave / G;     // value strides of a wavefront
+    for (int q0 = wv; q0 < nl; q0 += kWG / kWave) {
+        const int row = s_long[q0];
+        int rs, re;
+        range(row, rs, re);
+        const int ws = lane / G, wg = lane % G;
+        T a[KG];
+#pragma unroll
+        for (int q = 0; q < KG; ++q) a[q] = T(0);
+        for (int v = rs + ws; v < re; v += WS) term(v, wg, a);
+#pragma unroll
+        for (int q = 0; q < KG; ++q)
+            for (int d = G; d < kWave; d <<= 1) a[q] += __shfl_xor(a[q], d);
+        if (ws == 0) emit(row, wg, a);
+    }
+}
+
 // The bounds are uniform; readfirstlane keeps them (and the staging ranges
 // computed from them) in scalar registers.
 __device__ __forceinline__ TileBounds item_bounds(const BatchDescV &d, int64_t tile) {
@@ -372,21 +427,24 @@ void k_batch_v(const BatchDescV *__restrict__ descs, const int32_t *__restrict__
                         if (th == 0) L.nlong = 0;
                         __syncthreads();
                     }
-                    value_rows<T, KC>(
+                    // G lanes share a row sub-lane, KG right-hand sides each
+                    constexpr int G = KC >= 16 ? 4 : 1, KG = KC / G;
+                    value_rows_g<T, KG, G>(
                         np, range,
-                        [&](int v, T *acc) {
-                            T xa[KC];
-                            load_xrow<T, KC>(xb, L.vcol[v], ld, t0, xa);
+                        [&](int v, int g, T *acc) {
+                            T xa[KG];
+                            load_xrow<T, KG>(xb, L.vcol[v], ld, t0 + g * KG, xa);
                             const T a = sval[v];
 #pragma unroll
-                            for (int q = 0; q < KC; ++q) acc[q] = fma(a, xa[q], acc[q]);
+                            for (int q = 0; q < KG; ++q) acc[q] = fma(a, xa[q], acc[q]);
                         },
-                        [&](int pl, const T *acc) {
+                        [&](int pl, int g, const T *acc) {
                             const int64_t row = (int64_t)(b.p0 + pl);
+                            const int c0 = t0 + g * KG;
 #pragma unroll
-                            for (int q = 0; q < KC; ++q) {
-                                if (b.f) partial[w * ld + t0 + q] = acc[q];    // k_batch_fix
-                                else if (row < d.nrows) ((T *)d.Y)[row * ld + t0 + q] = acc[q];
+                            for (int q = 0; q < KG; ++q) {
+                                if (b.f) partial[w * ld + c0 + q] = acc[q];    // k_batch_fix
+                                else if (row < d.nrows) ((T *)d.Y)[row * ld + c0 + q] = acc[q];
                             }
                         },
                         L.longrow, &L.nlong);

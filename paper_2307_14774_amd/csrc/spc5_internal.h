@@ -33,6 +33,7 @@ struct spc5_matrix {
     int32_t *tile_f = nullptr;     // [ntiles_staged+1], piece slot + 1 of a piece tile, else 0
     int64_t ntiles_staged = 0;
     int max_tile_values = 0;       // largest tile, in values
+    int tile_bt = 0;               // block cap the schedule was built with
     bool staged_ok = false;        // the staged schedule exists
     int variant = 0;               // staged-kernel ablation variant (spc5_set_variant)
     // panels longer than a tile: panel, first and last piece tile
@@ -46,6 +47,15 @@ struct spc5_matrix {
     uint16_t *tr_lidx = nullptr;   // [nnz] pass 1: chunk-local value to write
     int32_t *tr_gpos = nullptr;    // [nnz] pass 1: staging slot written
     uint16_t *tr_src = nullptr;    // [nnz] pass 2: bucket-local slot read
+    void *tr_arow = nullptr;       // [nnz] A's row of every packed value (pass 1): uint16
+                                   // offsets from tr_cbase[chunk], or int32 when it is NULL
+    int32_t *tr_cbase = nullptr;   // [nbuckets] base row of every chunk of A
+    int32_t *tr_hoff = nullptr;    // [nbuckets+1] first nonempty A^T row of each bucket
+    int32_t *tr_hpos = nullptr;    // [nheads] first position of each nonempty A^T row
+    int32_t *tr_hrow = nullptr;    // [nheads] its row index
+    int64_t tr_nheads = 0;
+    int32_t *tr_edge_rows = nullptr;   // [3*nedge] (row, first bucket, last bucket)
+    int64_t tr_nedge = 0, tr_nbuckets = 0;
     // per-stream scratch of the products (see Scratch)
     spc5::ScratchPool *pool = nullptr;
 };
@@ -82,8 +92,9 @@ int validate_csr(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int3
 int auto_kernel(const spc5_matrix *A);
 
 // Scratch memory of one product call: the partial row sums of the piece
-// tiles of A (npieces*r values) and of A^T's plan, and the two buffers that
-// move caller values into A^T's packed order (nnz values each).  A call
+// tiles of A (npieces*r values) and of A^T's plan, and for a transpose with
+// caller values the staging of the products (nnz values) and the
+// bucket-edge partial sums (2 per bucket).  A call
 // writes all of it before reading it, so nothing needs clearing.  The normal
 // entry points take it from a pool of the handle with one set per stream
 // (calls on one stream are ordered, calls on different streams do not
@@ -92,7 +103,7 @@ struct Scratch {
     void *partial = nullptr;
     void *tr_partial = nullptr;
     void *stage = nullptr;
-    void *vals = nullptr;
+    void *edges = nullptr;
 };
 constexpr int kNeedPartial = 1, kNeedTrPartial = 2, kNeedTheta = 4;
 // Scratch of A for stream s with the parts `need` asks for, allocated on the
@@ -113,6 +124,9 @@ hipError_t launch_spmv_staged(const spc5_matrix *A, const void *val, const void 
 // (alone = false: full-size tiles).
 int build_staged_schedule(spc5_matrix *A, int ppw, bool alone = true);
 void free_staged_schedule(spc5_matrix *A);
+// Staged schedule for the ablation variants (which run the 16 KiB value
+// buffer and its block cap) when `variant`, else back to the default one.
+int fit_schedule_to_variants(spc5_matrix *A, bool variant);
 hipError_t excl_scan_i64(const int64_t *in, int64_t n, int64_t *out, hipStream_t s,
                          int64_t **scratch);
 int remap_enabled();
@@ -137,7 +151,7 @@ int finish_matrix(spc5_matrix *A);
 // Transposed-product plan of A (see spc5_prepare_transpose).
 int build_transpose_plan(spc5_matrix *A, int r, int c);
 // x_out = A^T y_in through the plan; vals overrides A's values (packed order).
-// sc.tr_partial serves A^T's piece tiles, sc.stage and sc.vals the value move.
+// Caller values: sc.stage and sc.edges; the matrix's own: sc.tr_partial.
 hipError_t launch_transpose_plan(const spc5_matrix *A, const void *vals, const void *ybar,
                                  void *xbar, hipStream_t s, const Scratch &sc);
 

@@ -12,17 +12,28 @@ namespace spc5 {
 constexpr int kWG = 256;   // threads per workgroup (4 wavefronts)
 constexpr int kXcdRun = 32; // consecutive workgroups kept on one XCD (xcd_chunks)
 
+// Blocks per tile for r > 1: bounded by the x windows in LDS (8 KiB, c
+// entries per block) and by one thread per block (256).  With the largest
+// value buffer (NVG = 4, 16 KiB) the cap is 224 blocks: 1 KiB less of
+// windows and per-block tables, which lets one more workgroup reside per
+// compute unit (FP64 beta(4,4): 6 instead of 5).  sz: value bytes, cm: c
+// rounded up to 4, 8 or 16.
+constexpr int stream_bt(int sz, int cm, int nvg) {
+    const int bt0 = 8192 / (cm * sz);
+    const int cap = nvg >= 4 ? 224 : 256;
+    return bt0 < cap ? bt0 : cap;
+}
+
 template <typename T, int R, int C, int NVG = 4>
 struct StreamCfg {
     using MT = typename MaskOf<C>::type;
     static constexpr int MB = (int)sizeof(MT);
     // LDS bytes for the values of one tile: NVG 16-byte vectors per thread
     static constexpr int VBYTES = 4096 * NVG;
-    static constexpr int BT0 = 8192 / (C * (int)sizeof(T));
-    // blocks per tile: bounded by the x windows in LDS (C per block); beta(1,c)
-    // keeps no windows (value mode) and gives each thread BPT blocks
+    // blocks per tile (stream_bt); beta(1,c) keeps no windows (value mode)
+    // and gives each thread BPT blocks
     static constexpr int BPT = R == 1 ? 4 : 1;
-    static constexpr int BT = R == 1 ? kWG * BPT : (BT0 < 256 ? BT0 : 256);
+    static constexpr int BT = R == 1 ? kWG * BPT : stream_bt((int)sizeof(T), C, NVG);
     static constexpr int PPW = kWG / R;                                // panels per tile
     static constexpr int VVEC = VBYTES / 16;
     static constexpr int MVEC = (BT * R * MB + 30) / 16;

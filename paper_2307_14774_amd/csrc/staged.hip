@@ -40,13 +40,21 @@
 
 namespace spc5 {
 
-// Tile capacities for a matrix (must match StreamCfg).
+// Tile capacities for a matrix (must match StreamCfg): values, blocks for
+// value buffers of at most 12 KiB, and panels.
 void staged_caps(const spc5_matrix *A, int *vt, int *bt, int *ppw) {
     const int sz = A->dtype == SPC5_F64 ? 8 : 4;
     const int cm = A->c <= 4 ? 4 : (A->c <= 8 ? 8 : 16);
     *vt = ((A->r == 1 ? value_tile(sz) * sz : 16384) - 16) / sz;
-    *bt = A->r == 1 ? 4 * kWG : std::min(256, 8192 / (cm * sz));
+    *bt = A->r == 1 ? 4 * kWG : stream_bt(sz, cm, 3);
     *ppw = kWG / A->r;
+}
+
+// Value buffer (NVG 16-byte vectors per thread: 1..4) the staged kernel
+// uses for tiles of at most maxv values.
+static int stream_nvg(int64_t maxv, int sz) {
+    const int64_t need = maxv * sz + 16;
+    return need <= 4096 ? 1 : need <= 8192 ? 2 : need <= 12288 ? 3 : 4;
 }
 
 // Rows phase of one staged tile: thread = (panel pl, sub-lane, row i) with S
@@ -486,13 +494,18 @@ __attribute__((amdgpu_waves_per_eu(vstream_residency<T, C, NVG>()))) void k_spmv
 
 // ---------------------------------------------------------------- schedule
 
-// Greedy tiles inside each group of ppw consecutive panels: a panel starts a
-// new tile when adding it would pass vt values or bt blocks.  A panel larger
+// Greedy tiles inside each group of kTileGroup*ppw consecutive panels: a
+// panel starts a new tile when adding it would pass vt values, bt blocks or
+// ppw panels.  A panel larger
 // than a whole tile is cut into pieces of at most vt values and bt blocks,
 // each a tile of its own flagged as a piece; the pieces' partial row sums
 // are added in a fixed order by k_split_fixup, so the result stays
 // reproducible.  One thread per group; pass 0 counts the tiles and the split
 // panels of each group, pass 1 writes them.
+// Tile groups are this many tile widths long: tiles never cross a group
+// edge, so a group much longer than a tile leaves few short tiles at edges.
+constexpr int kTileGroup = 8;
+
 __global__ void k_tile_groups(int pass, int64_t npanels, int ppw, int vt, int bt,
                               const int32_t *bp, const int32_t *pv, const int64_t *vpre,
                               int64_t *count, const int64_t *first, int64_t *scount,
@@ -500,9 +513,10 @@ __global__ void k_tile_groups(int pass, int64_t npanels, int ppw, int vt, int bt
                               int32_t *tf, int32_t *sp, int32_t *st0, int32_t *st1,
                               int *maxvals) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ng = (npanels + ppw - 1) / ppw;
+    const int64_t gw = (int64_t)kTileGroup * ppw;
+    const int64_t ng = (npanels + gw - 1) / gw;
     if (g >= ng) return;
-    const int64_t pa = g * ppw, pz = min(pa + ppw, npanels);
+    const int64_t pa = g * gw, pz = min(pa + gw, npanels);
     int64_t n = 0, o = pass ? first[g] : 0;
     int64_t ns = 0, so = pass ? sfirst[g] : 0;
     int64_t start = -1;   // first panel of the open tile, -1: none open
@@ -547,8 +561,8 @@ __global__ void k_tile_groups(int pass, int64_t npanels, int ppw, int vt, int bt
             ++ns;
             continue;
         }
-        const bool cut =
-            start >= 0 && (pv[p + 1] - pv[start] > vt || bp[p + 1] - bp[start] > bt);
+        const bool cut = start >= 0 && (pv[p + 1] - pv[start] > vt ||
+                                        bp[p + 1] - bp[start] > bt || p - start >= ppw);
         if (start < 0 || cut) {
             if (start >= 0) atomicMax(maxvals, pv[p] - pv[start]);
             emit(p, bp[p], pv[p], 0);
@@ -634,11 +648,64 @@ void free_staged_schedule(spc5_matrix *A) {
     A->npieces = 0;
 }
 
+static int build_schedule_bt(spc5_matrix *A, int ppw_req, bool alone, int bt_cap,
+                             int vt_cap = 0);
+static int stream_occupancy(const spc5_matrix *A, int nvg);
+
+// Tiles resident per compute unit over the launch: resident workgroups of
+// the kernel the schedule selects, per tile of the schedule.  Tiles of one
+// matrix carry the same bytes in total, so the larger this is, the more
+// bytes are in flight.
+static double schedule_score(const spc5_matrix *A) {
+    if (A->ntiles_staged == 0) return 0.0;
+    const int sz = A->dtype == SPC5_F64 ? 8 : 4;
+    return (double)stream_occupancy(A, stream_nvg(A->max_tile_values, sz)) /
+           (double)A->ntiles_staged;
+}
+
+// The staged schedule.  For r > 1 two tile sizes compete: values up to the
+// 12 KiB buffer with the full block cap, and up to 16 KiB with the 16 KiB
+// buffer's smaller block cap.  Larger tiles mean fewer tiles, but their
+// kernel may hold fewer workgroups per compute unit; the schedule with more
+// resident workgroups per tile is kept.
 int build_staged_schedule(spc5_matrix *A, int ppw_req, bool alone) {
+    int st = build_schedule_bt(A, ppw_req, alone, 0);
+    if (st != SPC5_OK || A->r == 1) return st;
+    const int sz = A->dtype == SPC5_F64 ? 8 : 4;
+    const int cm = A->c <= 4 ? 4 : (A->c <= 8 ? 8 : 16);
+    const int bt4 = stream_bt(sz, cm, 4);
+    if (stream_nvg(A->max_tile_values, sz) < 4) return st;    // 12 KiB holds every tile
+    // the 16 KiB buffer holds fewer blocks: rebuild with its cap, then
+    // compare with tiles capped at 12 KiB of values
+    if (bt4 < A->tile_bt && (st = build_schedule_bt(A, ppw_req, alone, bt4)) != SPC5_OK)
+        return st;
+    const double s4 = schedule_score(A);
+    const int vt3 = (12288 - 16) / sz;
+    if ((st = build_schedule_bt(A, ppw_req, alone, 0, vt3)) != SPC5_OK) return st;
+    const double s3 = schedule_score(A);
+    if (s4 > s3) st = build_schedule_bt(A, ppw_req, alone, bt4);
+    return st;
+}
+
+int fit_schedule_to_variants(spc5_matrix *A, bool variant) {
+    if (A->r == 1) return SPC5_OK;
+    const int sz = A->dtype == SPC5_F64 ? 8 : 4;
+    const int cm = A->c <= 4 ? 4 : (A->c <= 8 ? 8 : 16);
+    const int bt4 = stream_bt(sz, cm, 4);
+    if (variant) return A->tile_bt > bt4 ? build_schedule_bt(A, A->sppt, true, bt4) : SPC5_OK;
+    int vt, bt, ppw;
+    staged_caps(A, &vt, &bt, &ppw);
+    return A->tile_bt < bt ? build_staged_schedule(A, A->sppt) : SPC5_OK;
+}
+
+static int build_schedule_bt(spc5_matrix *A, int ppw_req, bool alone, int bt_cap,
+                             int vt_cap) {
     free_staged_schedule(A);
     A->staged_ok = true;
     int vt, bt, ppw;
     staged_caps(A, &vt, &bt, &ppw);
+    if (bt_cap > 0) bt = std::min(bt, bt_cap);
+    if (vt_cap > 0) vt = std::min(vt, vt_cap);
     if (ppw_req > 0) ppw = std::min(ppw, ppw_req);
     // small matrices launched alone: narrower tiles, so that there are about
     // 2048 of them to spread over the 256 compute units (a batch, which
@@ -648,6 +715,7 @@ int build_staged_schedule(spc5_matrix *A, int ppw_req, bool alone) {
         vt = (int)std::min<int64_t>(vt, std::max<int64_t>(256, A->nnz / 2048));
     }
     A->sppt = ppw;
+    A->tile_bt = bt;
     A->max_tile_values = 0;
     if (A->npanels == 0) return SPC5_OK;
     hipStream_t s = nullptr;
@@ -668,7 +736,8 @@ int build_staged_schedule(spc5_matrix *A, int ppw_req, bool alone) {
         return hip_fail(err, what);
     };
     const int64_t np = A->npanels;
-    const int64_t ng = (np + ppw - 1) / ppw;
+    const int64_t gw = (int64_t)kTileGroup * ppw;
+    const int64_t ng = (np + gw - 1) / gw;
     const unsigned grid = (unsigned)((ng + 255) / 256);
     const bool m8 = A->mask_bytes == 1;
     if ((e = hipMalloc((void **)&count, (size_t)ng * 8)) != hipSuccess ||
@@ -806,23 +875,68 @@ static bool sparse_rows(const spc5_matrix *A) {
     return A->nblocks > 0 && 2.0 * (double)A->nnz < (double)A->nblocks * A->r * A->c;
 }
 
+template <typename T, int R, int C, int NVG>
+static int occupancy_g(bool sparse) {
+    int blocks = 0;
+    const hipError_t e =
+        sparse ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                     &blocks, k_spmv_stream<T, R, C, NVG, true, 0>, kWG, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                     &blocks, k_spmv_stream<T, R, C, NVG, false, 0>, kWG, 0);
+    return e == hipSuccess ? blocks : 0;
+}
+
+template <typename T, int R, int C>
+static int occupancy_rc(bool sparse, int nvg) {
+    switch (nvg) {
+        case 1: return occupancy_g<T, R, C, 1>(sparse);
+        case 2: return occupancy_g<T, R, C, 2>(sparse);
+        case 3: return occupancy_g<T, R, C, 3>(sparse);
+        default: return occupancy_g<T, R, C, 4>(sparse);
+    }
+}
+
+template <typename T>
+static int occupancy_t(const spc5_matrix *A, int nvg) {
+    const bool sp = sparse_rows(A);
+#define SPC5_CASE(RR, CC) \
+    case RR * 100 + CC: return occupancy_rc<T, RR, CC>(sp, nvg);
+#define SPC5_ROW(RR) SPC5_CASE(RR, 4) SPC5_CASE(RR, 8) SPC5_CASE(RR, 16)
+    switch (A->r * 100 + (A->c <= 4 ? 4 : (A->c <= 8 ? 8 : 16))) {
+        SPC5_ROW(2) SPC5_ROW(3) SPC5_ROW(4) SPC5_ROW(5) SPC5_ROW(6) SPC5_ROW(7) SPC5_ROW(8)
+        default: return 0;
+    }
+#undef SPC5_ROW
+#undef SPC5_CASE
+}
+
+// Workgroups of the r > 1 staged kernel with value buffer nvg that one
+// compute unit holds (registers and LDS).
+static int stream_occupancy(const spc5_matrix *A, int nvg) {
+    return A->dtype == SPC5_F64 ? occupancy_t<double>(A, nvg) : occupancy_t<float>(A, nvg);
+}
+
 // LDS value buffer sized to the largest tile of the matrix: 4, 8, 12 or 16
 // KiB (value-mode tiles at most value_tile() values).
 template <typename T, int R, int C, bool SPARSE>
 static hipError_t launch_stream_s(const spc5_matrix *A, const T *val, const T *x, T *y,
                                   hipStream_t s, int remap, T *partial) {
-    const int64_t need = (int64_t)A->max_tile_values * (int64_t)sizeof(T) + 16;
-    if (need <= 4096)
+    const int nvg = stream_nvg(A->max_tile_values, (int)sizeof(T));
+    if (nvg == 1)
         return launch_stream_g<T, R, C, 1, SPARSE>(A, val, x, y, s, remap, partial);
-    if (need <= 8192)
+    if (nvg == 2)
         return launch_stream_g<T, R, C, 2, SPARSE>(A, val, x, y, s, remap, partial);
     // a 12 KiB buffer where the tiles fit: one more resident workgroup per
     // compute unit (FP64 beta(4,4) Laplacian: 6 instead of 5)
-    if (need <= 12288)
+    if (nvg == 3)
         return launch_stream_g<T, R, C, 3, SPARSE>(A, val, x, y, s, remap, partial);
-    // value-mode tiles stop at value_tile() values (8 or 12 KiB)
+    // value-mode tiles stop at value_tile() values (8 or 12 KiB); the 16 KiB
+    // buffer holds fewer blocks (the schedule was built for it)
     if constexpr (R == 1) return hipErrorInvalidValue;
-    else return launch_stream_g<T, R, C, 4, SPARSE>(A, val, x, y, s, remap, partial);
+    else {
+        if (A->tile_bt > StreamCfg<T, R, C, 4>::BT) return hipErrorInvalidValue;
+        return launch_stream_g<T, R, C, 4, SPARSE>(A, val, x, y, s, remap, partial);
+    }
 }
 
 template <typename T, int R, int C>
@@ -832,6 +946,9 @@ static hipError_t launch_stream(const spc5_matrix *A, const T *val, const T *x, 
     constexpr bool kVarShape = (R == 2 || R == 4 || R == 8) && (C == 4 || C == 8);
     if (A->variant != 0) {
         if constexpr (kVarShape) {
+            // the variants run the 16 KiB value buffer (spc5_set_variant
+            // fitted the schedule to its block cap)
+            if (A->tile_bt > StreamCfg<T, R, C, 4>::BT) return hipErrorInvalidValue;
             switch (A->variant) {
                 case kVarPartialX:
                     return launch_stream_g<T, R, C, 4, false, kVarPartialX>(A, val, x, y, s,

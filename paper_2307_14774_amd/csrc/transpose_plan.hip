@@ -16,17 +16,23 @@
 //  3. convert that CSR to beta(r,c) with the ordinary conversion, placing
 //     A's values and, as an int32 payload, A's packed index of every entry:
 //     the permutation perm (A^T's value q is A's value perm[q]);
-//  4. split perm for caller-supplied values theta.  A single gather
-//     theta[perm[q]] reads one scattered word per cache line (perm jumps
-//     across all of A for every row of A^T).  Instead A^T's packed order is
-//     cut into buckets of W = 16384 values (one LDS window), A's values
-//     get staging slots grouped by bucket (inside a bucket: A's packed
-//     order), and two passes move them, each through LDS: pass 1 loads a
-//     contiguous chunk of W values of A into LDS and writes them out in slot
-//     order (one contiguous run per bucket); pass 2 loads one bucket's slots
-//     into LDS and writes the bucket's values of A^T in order.  Every global
-//     read and write is contiguous; the permutations happen in LDS, with
-//     16-bit local indices.
+//  4. tables for caller-supplied values theta (autograd).  Then the
+//     transpose does not run the forward kernel over A^T at all: with
+//     p_k = theta_k * ybar[row_k] (one product per nonzero, formed in A's
+//     packed order, where ybar is read row after row), x_bar[j] is the sum
+//     of the p's of A^T's row j, i.e. a segmented sum of p in A^T's CSR
+//     order.  A single gather p[order[q]] would read one scattered word per
+//     cache line, so A^T's CSR order is cut into buckets of W = 16384
+//     positions (one LDS window), A's values get staging slots grouped by
+//     bucket (inside a bucket: A's packed order), and two passes run, each
+//     through LDS: pass 1 loads a contiguous chunk of W values of A, forms
+//     their products and writes them out in slot order (one contiguous run
+//     per bucket); pass 2 loads one bucket's slots, reads them in A^T's
+//     order through 16-bit local indices and sums each row's run with a
+//     workgroup segmented scan.  A row inside one bucket is stored there;
+//     a row cut by bucket edges leaves its bucket-edge partial sums, added
+//     in bucket order by a fixup.  Every global access is contiguous, there
+//     are no atomics, and the result is reproducible bit for bit.
 #include "spc5_internal.h"
 #include "wave.h"
 
@@ -34,6 +40,7 @@
 #include <rocprim/iterator/counting_iterator.hpp>
 
 #include <algorithm>
+#include <vector>
 
 namespace spc5 {
 
@@ -127,18 +134,16 @@ __global__ void k_chunk_lists(int64_t nnz, int64_t w, const int32_t *__restrict_
     if (j < nnz) lidx[j] = (uint16_t)(order[by_chunk[j]] - (j / w) * w);
 }
 
-// Pass 1: workgroup c loads values [c*W, c*W + m) of A into LDS, then writes
-// stage[gpos[j]] = win[lidx[j]] over its slot-ordered list.  Each thread
-// takes pairs of neighbouring entries, so the index tables load as one 64-bit
-// (gpos) and one 32-bit (lidx) word per pair; a pair at the end of the
-// tables reads into their 64 bytes of trailing padding, and its second entry
-// is dropped.
-template <typename T>
-__global__ __launch_bounds__(kMoveThreads) void k_move_chunks(int64_t n,
-                                                              const uint16_t *__restrict__ lidx,
-                                                              const int32_t *__restrict__ gpos,
-                                                              const T *__restrict__ in,
-                                                              T *__restrict__ stage) {
+// Pass 1: workgroup c loads values [c*W, c*W + m) of A into LDS, each
+// multiplied by ybar at its row, then writes stage[gpos[j]] = win[lidx[j]]
+// over its slot-ordered list.  Each thread handles pairs of consecutive
+// list entries (8-byte slot and 4-byte local-index loads).  Rows come as
+// 16-bit offsets from the chunk's base row (R16) or as full indices.
+template <typename T, bool R16>
+__global__ __launch_bounds__(kMoveThreads) void k_move_products(
+    int64_t n, const uint16_t *__restrict__ lidx, const int32_t *__restrict__ gpos,
+    const T *__restrict__ in, const void *__restrict__ arow, const int32_t *__restrict__ cbase,
+    const T *__restrict__ ybar, T *__restrict__ stage) {
     constexpr int W = kMoveValues;
     constexpr int P = W / (2 * kMoveThreads);
     __shared__ T win[W];
@@ -153,11 +158,24 @@ __global__ __launch_bounds__(kMoveThreads) void k_move_chunks(int64_t n,
         g[e] = k < m ? *(const uint64_t *)(gpos + c0 + k) : 0;
         l[e] = k < m ? *(const uint32_t *)(lidx + c0 + k) : 0;
     }
+    if constexpr (R16) {
+        const uint16_t *rr = (const uint16_t *)arow;
+        const int rb = cbase[blockIdx.x];
 #pragma unroll
-    for (int e = 0; e < P; ++e) {
-        const int k = 2 * (th + e * kMoveThreads);
-        if (k < m) win[k] = in[c0 + k];
-        if (k + 1 < m) win[k + 1] = in[c0 + k + 1];
+        for (int e = 0; e < P; ++e) {
+            const int k = 2 * (th + e * kMoveThreads);
+            const uint32_t rp = k < m ? *(const uint32_t *)(rr + c0 + k) : 0u;
+            if (k < m) win[k] = in[c0 + k] * ybar[rb + (int)(rp & 0xffffu)];
+            if (k + 1 < m) win[k + 1] = in[c0 + k + 1] * ybar[rb + (int)(rp >> 16)];
+        }
+    } else {
+        const int32_t *rr = (const int32_t *)arow;
+#pragma unroll
+        for (int e = 0; e < P; ++e) {
+            const int k = 2 * (th + e * kMoveThreads);
+            if (k < m) win[k] = in[c0 + k] * ybar[rr[c0 + k]];
+            if (k + 1 < m) win[k + 1] = in[c0 + k + 1] * ybar[rr[c0 + k + 1]];
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -168,49 +186,251 @@ __global__ __launch_bounds__(kMoveThreads) void k_move_chunks(int64_t n,
     }
 }
 
-// Pass 2: workgroup b loads bucket b's slots [b*W, b*W + m) into LDS, then
-// writes out[b*W + q] = win[src[b*W + q]]; pairs as in pass 1.
+// Base row of every chunk of W packed values of A (the first row of its
+// first value's panel) and a flag when some chunk spans 65536 rows or more.
+__global__ void k_chunk_base(int64_t nnz, int64_t w, int r, const int32_t *__restrict__ row_of,
+                             int32_t *__restrict__ cbase, int *__restrict__ wide) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c * w >= nnz) return;
+    const int64_t last = min((c + 1) * w, nnz) - 1;
+    const int32_t b = row_of[c * w] / r * r;
+    const int32_t top = row_of[last] / r * r + r - 1;
+    cbase[c] = b;
+    if (top - b >= 65536) *wide = 1;
+}
+
+__global__ void k_rows16(int64_t nnz, int64_t w, const int32_t *__restrict__ row_of,
+                         const int32_t *__restrict__ cbase, uint16_t *__restrict__ rows16) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nnz) rows16[k] = (uint16_t)(row_of[k] - cbase[k / w]);
+}
+
+// Positions of a bucket per thread in pass 2 (consecutive).
+constexpr int kSumPer = kMoveValues / kMoveThreads;
+static_assert(kSumPer == 16, "two 16-byte loads of 16-bit indices per thread");
+
+// Segmented-sum operator: (head seen, sum since the last head).
 template <typename T>
-__global__ __launch_bounds__(kMoveThreads) void k_move_buckets(int64_t n,
-                                                               const uint16_t *__restrict__ src,
-                                                               const T *__restrict__ stage,
-                                                               T *__restrict__ out) {
+struct SegSum {
+    int f;
+    T v;
+};
+
+template <typename T>
+__device__ __forceinline__ SegSum<T> seg_join(SegSum<T> a, SegSum<T> b) {
+    return {a.f | b.f, b.f ? b.v : a.v + b.v};
+}
+
+// Pass 2: workgroup b loads bucket b's slots [b*W, b*W + m) into LDS.
+// Thread t owns positions t*16 .. t*16+15 of the bucket in A^T's CSR order;
+// position q's product is win[src[q]].  The heads of the bucket (first
+// positions of the nonempty rows that start in it, hpos[hoff[b]..hoff[b+1]),
+// rows hrow[...]) are flagged in LDS; a workgroup segmented scan carries each
+// row's running sum, and the number of heads, across threads.  A row that
+// starts and ends in the bucket is stored in xbar; the segment of the row
+// that started in an earlier bucket goes to head[b], the segment of a row
+// that starts here and goes on goes to tail[b] (k_edge_fixup adds them).
+// Empty rows keep the zero written before the pass.
+template <typename T>
+__global__ __launch_bounds__(kMoveThreads) void k_bucket_sums(
+    int64_t n, int nheads, const uint16_t *__restrict__ src, const T *__restrict__ stage,
+    const int32_t *__restrict__ hoff, const int32_t *__restrict__ hpos,
+    const int32_t *__restrict__ hrow, T *__restrict__ head, T *__restrict__ tail,
+    T *__restrict__ xbar) {
     constexpr int W = kMoveValues;
-    constexpr int P = W / (2 * kMoveThreads);
+    constexpr int NWV = kMoveThreads / kWave;
+    constexpr int VPL = 16 / (int)sizeof(T);            // values per 16-byte load
+    constexpr int NLD = kSumPer / VPL;                   // loads per thread
     __shared__ T win[W];
-    const int64_t q0 = (int64_t)blockIdx.x * W;
+    __shared__ uint32_t flags[W / 32 + 1];
+    __shared__ int s_f[NWV], s_c[NWV];
+    __shared__ T s_v[NWV];
+    const int b = blockIdx.x;
+    const int64_t q0 = (int64_t)b * W;
     const int m = (int)min((int64_t)W, n - q0);
-    const int th = threadIdx.x;
-    uint32_t l[P];
+    const int th = threadIdx.x, lane = lane_id(), wv = th / kWave;
+    const int t0 = th * kSumPer;
+    const int h0 = hoff[b], h1 = hoff[b + 1];
+    // every global read of the pass that does not depend on the scan, issued
+    // together: the bucket's slots (16 consecutive values per thread; the
+    // staging array is padded past its end), this thread's 16 positions'
+    // slot indices, and the first positions of up to 16 of the bucket's
+    // heads (a bucket has at most W = 16 * kMoveThreads of them)
+    typedef unsigned v4 __attribute__((ext_vector_type(4)));
+    v4 r[NLD];
+    {
+        const v4 *sp = (const v4 *)(stage + q0 + t0);
 #pragma unroll
-    for (int e = 0; e < P; ++e) {
-        const int k = 2 * (th + e * kMoveThreads);
-        l[e] = k < m ? *(const uint32_t *)(src + q0 + k) : 0;
+        for (int g = 0; g < NLD; ++g) r[g] = t0 < m ? sp[g] : v4{0u, 0u, 0u, 0u};
     }
+    v4 w0 = {0u, 0u, 0u, 0u}, w1 = {0u, 0u, 0u, 0u};
+    if (t0 < m) {
+        const v4 *sp = (const v4 *)(src + q0 + t0);
+        w0 = sp[0];
+        w1 = sp[1];
+    }
+    int hp[kSumPer];
 #pragma unroll
-    for (int e = 0; e < P; ++e) {
-        const int k = 2 * (th + e * kMoveThreads);
-        if (k < m) win[k] = stage[q0 + k];
-        if (k + 1 < m) win[k + 1] = stage[q0 + k + 1];
+    for (int i = 0; i < kSumPer; ++i) {
+        const int k = h0 + th + i * kMoveThreads;
+        hp[i] = k < h1 ? hpos[k] : -1;
     }
+    {
+        v4 *wp = (v4 *)(win + t0);
+#pragma unroll
+        for (int g = 0; g < NLD; ++g) wp[g] = r[g];
+    }
+    for (int k = th; k < W / 32 + 1; k += kMoveThreads) flags[k] = 0u;
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < P; ++e) {
-        const int k = 2 * (th + e * kMoveThreads);
-        if (k < m) out[q0 + k] = win[l[e] & 0xffffu];
-        if (k + 1 < m) out[q0 + k + 1] = win[l[e] >> 16];
+    for (int i = 0; i < kSumPer; ++i) {
+        if (hp[i] >= 0) {
+            const int pos = hp[i] - (int)q0;
+            atomicOr(&flags[pos >> 5], 1u << (pos & 31));
+        }
+    }
+    __syncthreads();
+    // products of this thread's positions and their head bits (bit 16: the
+    // next thread's first position)
+    T p[kSumPer];
+    {
+        const unsigned wd[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+        for (int i = 0; i < kSumPer; ++i) {
+            const unsigned idx = (wd[i >> 1] >> (16 * (i & 1))) & 0xffffu;
+            p[i] = t0 + i < m ? win[idx] : T(0);
+        }
+    }
+    const uint64_t fw = (uint64_t)flags[t0 >> 5] | ((uint64_t)flags[(t0 >> 5) + 1] << 32);
+    const unsigned hb = (unsigned)(fw >> (t0 & 31)) & 0x1ffffu;
+    // thread aggregate: (head seen, open segment's sum), head count
+    SegSum<T> agg = {0, T(0)};
+#pragma unroll
+    for (int i = 0; i < kSumPer; ++i) {
+        const bool h = (hb >> i) & 1u;
+        agg.v = h ? p[i] : agg.v + p[i];
+        agg.f |= h ? 1 : 0;
+    }
+    const int cnt = __popc(hb & 0xffffu);
+    // workgroup exclusive scans: segmented sums and head counts
+    SegSum<T> inc = agg;
+    int cinc = cnt;
+    for (int d = 1; d < kWave; d <<= 1) {
+        SegSum<T> o;
+        o.f = __shfl_up(inc.f, d);
+        o.v = __shfl_up(inc.v, d);
+        const int oc = __shfl_up(cinc, d);
+        if (lane >= d) {
+            inc = seg_join(o, inc);
+            cinc += oc;
+        }
+    }
+    if (lane == kWave - 1) {
+        s_f[wv] = inc.f;
+        s_v[wv] = inc.v;
+        s_c[wv] = cinc;
+    }
+    SegSum<T> exw;
+    exw.f = __shfl_up(inc.f, 1);
+    exw.v = __shfl_up(inc.v, 1);
+    int cex = __shfl_up(cinc, 1);
+    if (lane == 0) {
+        exw = {0, T(0)};
+        cex = 0;
+    }
+    __syncthreads();
+    SegSum<T> carry = {0, T(0)};
+    int heads_before = 0;
+    for (int w2 = 0; w2 < wv; ++w2) {
+        carry = seg_join(carry, SegSum<T>{s_f[w2], s_v[w2]});
+        heads_before += s_c[w2];
+    }
+    carry = seg_join(carry, exw);
+    heads_before += cex;
+    if (t0 >= m) return;
+    // rows of the segments ending in this thread: the open segment's head
+    // (h0-1: an earlier bucket's) and this thread's heads, read together
+    const int kin = h0 + heads_before - 1;
+    int rows[kSumPer + 1];
+#pragma unroll
+    for (int i = 0; i <= kSumPer; ++i) {
+        const int k = kin + i;
+        rows[i] = i <= cnt && k >= h0 ? hrow[k] : -1;
+    }
+    // walk the positions; a segment ends at e when e+1 is a head or e is the
+    // bucket's last position
+    T run = carry.v;
+    int kk = 0;                         // heads of this thread passed
+#pragma unroll
+    for (int i = 0; i < kSumPer; ++i) {
+        const int e = t0 + i;
+        if (e < m) {
+            if ((hb >> i) & 1u) {
+                run = T(0);
+                ++kk;
+            }
+            run += p[i];
+            const bool last = e == m - 1;
+            if (last || ((hb >> (i + 1)) & 1u)) {
+                const int k = kin + kk;
+                if (k < h0) {
+                    head[b] = run;              // started in an earlier bucket
+                } else {
+                    // the row goes on past the bucket when this is the last
+                    // position and the next row does not start right after it
+                    const bool after = last && q0 + m < n &&
+                                       (k + 1 >= nheads || hpos[k + 1] != (int)(q0 + m));
+                    if (after) tail[b] = run;
+                    else xbar[rows[kk]] = run;
+                }
+            }
+        }
     }
 }
 
+// Rows of A^T cut by bucket edges: x_bar[j] = tail[bs] + head[bs+1] + ... +
+// head[be], one wavefront per row, lanes striding the heads in bucket
+// order, then a butterfly: a fixed order, so the result is reproducible.
 template <typename T>
-static void launch_move(const spc5_matrix *A, const T *vals, hipStream_t s, T *stage, T *out) {
+__global__ __launch_bounds__(256) void k_edge_fixup(int64_t nrows, const int32_t *__restrict__ rows,
+                                                    const T *__restrict__ head,
+                                                    const T *__restrict__ tail,
+                                                    T *__restrict__ xbar) {
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (q >= nrows) return;    // uniform over the wavefront
+    const int lane = lane_id();
+    const int j = rows[3 * q], bs = rows[3 * q + 1], be = rows[3 * q + 2];
+    T acc = T(0);
+    for (int bb = bs + 1 + lane; bb <= be; bb += kWave) acc += head[bb];
+    for (int d = 1; d < kWave; d <<= 1) acc += __shfl_xor(acc, d);
+    if (lane == 0) xbar[j] = tail[bs] + acc;
+}
+
+template <typename T>
+static hipError_t launch_theta_transpose(const spc5_matrix *A, const T *vals, const T *ybar,
+                                         T *xbar, hipStream_t s, T *stage, T *edges) {
     constexpr int64_t W = kMoveValues;
     const int64_t n = A->nnz;
+    // rows without entries stay zero
+    hipError_t e = zero_fill(xbar, A->ncols, (int)sizeof(T), s);
+    if (e != hipSuccess || n == 0) return e;
     const unsigned grid = (unsigned)((n + W - 1) / W);
-    hipLaunchKernelGGL(k_move_chunks<T>, dim3(grid), dim3(kMoveThreads), 0, s, n, A->tr_lidx,
-                       A->tr_gpos, vals, stage);
-    hipLaunchKernelGGL(k_move_buckets<T>, dim3(grid), dim3(kMoveThreads), 0, s, n, A->tr_src,
-                       (const T *)stage, out);
+    T *head = edges, *tail = edges + grid;
+    if (A->tr_cbase)
+        hipLaunchKernelGGL((k_move_products<T, true>), dim3(grid), dim3(kMoveThreads), 0, s, n,
+                           A->tr_lidx, A->tr_gpos, vals, A->tr_arow, A->tr_cbase, ybar, stage);
+    else
+        hipLaunchKernelGGL((k_move_products<T, false>), dim3(grid), dim3(kMoveThreads), 0, s, n,
+                           A->tr_lidx, A->tr_gpos, vals, A->tr_arow, A->tr_cbase, ybar, stage);
+    hipLaunchKernelGGL(k_bucket_sums<T>, dim3(grid), dim3(kMoveThreads), 0, s, n,
+                       (int)A->tr_nheads, A->tr_src, (const T *)stage, A->tr_hoff, A->tr_hpos,
+                       A->tr_hrow, head, tail, xbar);
+    if (A->tr_nedge > 0) {
+        const int64_t thr = A->tr_nedge * kWave;
+        hipLaunchKernelGGL(k_edge_fixup<T>, dim3((unsigned)((thr + 255) / 256)), dim3(256), 0, s,
+                           A->tr_nedge, A->tr_edge_rows, (const T *)head, (const T *)tail, xbar);
+    }
+    return hipGetLastError();
 }
 
 int build_transpose_plan(spc5_matrix *A, int r, int c) {
@@ -223,7 +443,10 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     int64_t *rowptr_t = nullptr;
     void *val_t = nullptr, *tmp = nullptr;
     spc5_matrix *T = nullptr;
-    int32_t *perm = nullptr;
+    int32_t *perm = nullptr, *hoff = nullptr, *hpos = nullptr, *hrow = nullptr;
+    int32_t *cbase = nullptr;
+    void *arow = nullptr;
+    int32_t *edge_rows = nullptr;
     uint16_t *lidx = nullptr, *src = nullptr;
     size_t tmp_bytes = 0;
     auto cleanup = [&]() {
@@ -234,7 +457,8 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     auto fail_all = [&](int st) {
         cleanup();
         free_matrix(T);
-        for (void *p : {(void *)perm, (void *)lidx, (void *)src})
+        for (void *p : {(void *)perm, (void *)lidx, (void *)src, arow, (void *)hoff,
+                        (void *)hpos, (void *)hrow, (void *)edge_rows, (void *)cbase})
             if (p) (void)hipFree(p);
         return st;
     };
@@ -299,18 +523,92 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     T->mask_bytes = c <= 8 ? 1 : 2;
     T->npanels = (T->nrows + r - 1) / r;
     T->device = A->device;
-    if ((e = hipMalloc((void **)&perm, nz * 4 + kPad)) != hipSuccess)
-        return fail_all(hip_fail(e, "allocating the transpose plan"));
-    int st = convert_on_device(T, rowptr_t, colidx_t, val_t, idx_s, perm);
+    int st = convert_on_device(T, rowptr_t, colidx_t, val_t);
     if (st != SPC5_OK) return fail_all(st);
     if ((st = finish_matrix(T)) != SPC5_OK) return fail_all(st);
-    // 4. the value move's tables (row_of, col_of, key_s, idx_s and colidx_t
-    // are free again).  Slots: a stable sort of A's packed indices by the
-    // bucket of their A^T position; pass 1's lists: a stable sort of the
-    // slots by the chunk of A they read.
-    if ((e = hipMalloc((void **)&lidx, nz * 2 + kPad)) != hipSuccess ||
-        (e = hipMalloc((void **)&src, nz * 2 + kPad)) != hipSuccess)
+    // 4. the tables of the theta transpose (col_of, key_s and colidx_t are
+    // free again; idx_s is A^T's CSR order).  Slots: a stable sort of A's
+    // packed indices by the bucket of their A^T position; pass 1's lists: a
+    // stable sort of the slots by the chunk of A they read.  A's row of
+    // every packed value is kept for pass 1; for pass 2 the first position
+    // and the row of every nonempty row of A^T, grouped by bucket, and the
+    // rows cut by bucket edges.
+    const int64_t W = kMoveValues;
+    const int64_t nbk = (nnz + W - 1) / W;
+    if ((e = hipMalloc((void **)&perm, nz * 4 + kPad)) != hipSuccess ||
+        (e = hipMalloc((void **)&lidx, nz * 2 + kPad)) != hipSuccess ||
+        (e = hipMalloc((void **)&src, nz * 2 + kPad)) != hipSuccess ||
+        (e = hipMalloc((void **)&hoff, (size_t)(nbk + 1) * 4 + kPad)) != hipSuccess)
         return fail_all(hip_fail(e, "allocating the transpose plan"));
+    // A's rows for pass 1: 16-bit offsets from each chunk's base row when
+    // every chunk spans fewer than 65536 rows, else 32-bit rows
+    if (nnz > 0) {
+        int *wide = nullptr;
+        int hw = 0;
+        if ((e = hipMalloc((void **)&cbase, (size_t)nbk * 4 + kPad)) != hipSuccess ||
+            (e = hipMalloc((void **)&wide, 4)) != hipSuccess)
+            return fail_all(hip_fail(e, "allocating the transpose plan"));
+        if ((e = zero_fill(wide, 1, 4, s)) == hipSuccess) {
+            hipLaunchKernelGGL(k_chunk_base, dim3((unsigned)((nbk + 255) / 256)), dim3(256), 0, s,
+                               nnz, W, A->r, row_of, cbase, wide);
+            e = hipMemcpy(&hw, wide, 4, hipMemcpyDeviceToHost);
+        }
+        (void)hipFree(wide);
+        if (e != hipSuccess) return fail_all(hip_fail(e, "chunk rows"));
+        if (!hw) {
+            if ((e = hipMalloc(&arow, nz * 2 + kPad)) != hipSuccess)
+                return fail_all(hip_fail(e, "allocating the transpose plan"));
+            hipLaunchKernelGGL(k_rows16, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz,
+                               W, row_of, cbase, (uint16_t *)arow);
+        } else {
+            (void)hipFree(cbase);
+            cbase = nullptr;
+            if ((e = hipMalloc(&arow, nz * 4 + kPad)) != hipSuccess ||
+                (e = hipMemcpyAsync(arow, row_of, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s)) !=
+                    hipSuccess)
+                return fail_all(hip_fail(e, "keeping the rows of A"));
+        }
+    }
+    int64_t nedge = 0, nheads = 0;
+    {
+        std::vector<int64_t> rp((size_t)A->ncols + 1);
+        if ((e = hipMemcpy(rp.data(), rowptr_t, rp.size() * 8, hipMemcpyDeviceToHost)) !=
+            hipSuccess)
+            return fail_all(hip_fail(e, "reading the rowptr of A^T"));
+        std::vector<int32_t> hp, hr, ho((size_t)nbk + 1, 0), er;
+        for (int64_t jj = 0; jj < A->ncols; ++jj) {
+            if (rp[jj + 1] == rp[jj]) continue;
+            hp.push_back((int32_t)rp[jj]);
+            hr.push_back((int32_t)jj);
+            ++ho[(size_t)(rp[jj] / W) + 1];
+            const int64_t bs = rp[jj] / W, be = (rp[jj + 1] - 1) / W;
+            if (bs != be) {
+                er.push_back((int32_t)jj);
+                er.push_back((int32_t)bs);
+                er.push_back((int32_t)be);
+            }
+        }
+        for (int64_t bk = 0; bk < nbk; ++bk) ho[bk + 1] += ho[bk];
+        nheads = (int64_t)hp.size();
+        nedge = (int64_t)er.size() / 3;
+        if ((e = hipMalloc((void **)&hpos, std::max<size_t>(hp.size(), 1) * 4 + kPad)) !=
+                hipSuccess ||
+            (e = hipMalloc((void **)&hrow, std::max<size_t>(hr.size(), 1) * 4 + kPad)) !=
+                hipSuccess ||
+            (e = hipMalloc((void **)&edge_rows, std::max<size_t>(er.size(), 3) * 4)) !=
+                hipSuccess ||
+            (e = hipMemcpy(hoff, ho.data(), ho.size() * 4, hipMemcpyHostToDevice)) !=
+                hipSuccess ||
+            (!hp.empty() &&
+             ((e = hipMemcpy(hpos, hp.data(), hp.size() * 4, hipMemcpyHostToDevice)) !=
+                  hipSuccess ||
+              (e = hipMemcpy(hrow, hr.data(), hr.size() * 4, hipMemcpyHostToDevice)) !=
+                  hipSuccess)) ||
+            (!er.empty() &&
+             (e = hipMemcpy(edge_rows, er.data(), er.size() * 4, hipMemcpyHostToDevice)) !=
+                 hipSuccess))
+            return fail_all(hip_fail(e, "uploading the bucket tables"));
+    }
     if (nnz > 0) {
         const int64_t w = kMoveValues;
         const unsigned grid = (unsigned)((nnz + 255) / 256);
@@ -333,11 +631,11 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
                                              (size_t)nnz, 0u, bits, s);
         };
         // order[t] (key_s): the value of A in slot t; slot (col_of) its inverse
-        hipLaunchKernelGGL(k_bucket_keys, dim3(grid), dim3(256), 0, s, nnz, w, perm, row_of);
+        hipLaunchKernelGGL(k_bucket_keys, dim3(grid), dim3(256), 0, s, nnz, w, idx_s, row_of);
         if ((e = sort(row_of, col_of, key_s)) != hipSuccess)
             return fail_all(hip_fail(e, "sorting by bucket"));
         hipLaunchKernelGGL(k_invert, dim3(grid), dim3(256), 0, s, nnz, key_s, col_of);
-        hipLaunchKernelGGL(k_bucket_src, dim3(grid), dim3(256), 0, s, nnz, w, col_of, perm, src);
+        hipLaunchKernelGGL(k_bucket_src, dim3(grid), dim3(256), 0, s, nnz, w, col_of, idx_s, src);
         // pass 1 lists: slots sorted by chunk (stable, so ascending inside a
         // chunk); gpos (perm's memory) = the slots, lidx = local value index
         hipLaunchKernelGGL(k_chunk_keys, dim3(grid), dim3(256), 0, s, nnz, w, key_s, row_of);
@@ -347,31 +645,40 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
         if ((e = hipGetLastError()) != hipSuccess)
             return fail_all(hip_fail(e, "building the value move"));
     }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+        return fail_all(hip_fail(e, "building the transpose plan"));
     cleanup();
     A->tr = T;
     A->tr_lidx = lidx;
     A->tr_gpos = perm;
     A->tr_src = src;
+    A->tr_arow = arow;
+    A->tr_cbase = cbase;
+    A->tr_hoff = hoff;
+    A->tr_hpos = hpos;
+    A->tr_hrow = hrow;
+    A->tr_nheads = nheads;
+    A->tr_edge_rows = edge_rows;
+    A->tr_nedge = nedge;
+    A->tr_nbuckets = nbk;
     return SPC5_OK;
 }
 
 hipError_t launch_transpose_plan(const spc5_matrix *A, const void *vals, const void *ybar,
                                  void *xbar, hipStream_t s, const Scratch &sc) {
-    const spc5_matrix *T = A->tr;
-    const void *tv = T->val;
-    if (vals && A->nnz > 0) {
-        // the caller's values (A's packed order) moved to A^T's packed order
-        if (!sc.stage || !sc.vals) return hipErrorInvalidValue;
-        if (A->dtype == SPC5_F64)
-            launch_move<double>(A, (const double *)vals, s, (double *)sc.stage,
-                                (double *)sc.vals);
-        else
-            launch_move<float>(A, (const float *)vals, s, (float *)sc.stage, (float *)sc.vals);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        tv = sc.vals;
+    if (vals) {
+        // caller values theta: products in A's order, segmented sums in A^T's
+        if (A->nnz > 0 && (!sc.stage || !sc.edges)) return hipErrorInvalidValue;
+        return A->dtype == SPC5_F64
+                   ? launch_theta_transpose<double>(A, (const double *)vals,
+                                                    (const double *)ybar, (double *)xbar, s,
+                                                    (double *)sc.stage, (double *)sc.edges)
+                   : launch_theta_transpose<float>(A, (const float *)vals, (const float *)ybar,
+                                                   (float *)xbar, s, (float *)sc.stage,
+                                                   (float *)sc.edges);
     }
-    return launch_spmv(T, tv, ybar, xbar, s, sc.tr_partial);
+    // the matrix's own values: the forward kernel over the stored A^T
+    return launch_spmv(A->tr, A->tr->val, ybar, xbar, s, sc.tr_partial);
 }
 
 }  // namespace spc5
