@@ -61,21 +61,23 @@ def log(msg):
 
 
 WORKLOADS = {   # name -> (tag, beta(r,c) of the timed product)
-    "laplacian": ("laplacian2d_2048 fp64", (4, 4)),
-    "fem": ("fem3d_96x3 fp64", (4, 4)),
-    "random": ("random10k fp64", (1, 8)),
+    "laplacian": ("laplacian2d_2048", (4, 4)),
+    "fem": ("fem3d_96x3", (4, 4)),
+    "random": ("random10k", (1, 8)),
+    "zipf": ("zipf_graph_2^20", (1, 8)),
 }
 
 
-def make_workload(name):
+def make_workload(name, dtype="float64"):
     from paper_2307_14774_amd import workloads as W
     if name not in WORKLOADS:
         raise SystemExit(f"unknown workload {name}")
     tag, rc = WORKLOADS[name]
     A = {"laplacian": lambda: W.laplacian_2d(2048, seed=0),
          "fem": lambda: W.fem_3d(96, seed=0),
-         "random": lambda: W.random_uniform(10_000, 10, seed=0)}[name]()
-    return A, rc, tag
+         "random": lambda: W.random_uniform(10_000, 10, seed=0),
+         "zipf": lambda: W.zipf_graph(1 << 20, seed=0)}[name]()
+    return A, rc, tag + (" fp64" if dtype == "float64" else " fp32")
 
 
 def time_launches(fn, steps, warmup, flush=None):
@@ -155,12 +157,12 @@ def _counter_means(path, counter):
     return {name: (t / n, n) for name, (n, t) in sums.items()}
 
 
-def traffic_write(fetch_csv, write_csv, workload):
+def traffic_write(fetch_csv, write_csv, workload, dtype="float64"):
     """Scale the forward kernel's FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
     by what the same counters read for the calibration copy (COPY_ELEMS
     float64 read and written once) and store bytes per launch."""
     tag, rc = WORKLOADS[workload]
-    tag = tag + f" beta({rc[0]},{rc[1]})"
+    tag = tag + (" fp64" if dtype == "float64" else " fp32") + f" beta({rc[0]},{rc[1]})"
     fetch = _counter_means(fetch_csv, "FETCH_SIZE")
     write = _counter_means(write_csv, "WRITE_SIZE")
 
@@ -489,7 +491,7 @@ def backward_extras(dev):
     return res
 
 
-def batch_extras(dev, nmat=256, ks=(1, 4, 16)):
+def batch_extras(dev, nmat=256, ks=(1, 4, 16), dtypes=("float64", "float32")):
     """Batched workload: `nmat` uneven matrices (log-uniform 1k..200k rows,
     Zipf(1.5) row lengths capped at 512, 30% of nonzeros in runs), beta(r,c)
     per matrix from the byte-model autotuner and each matrix's batch tile cap
@@ -524,6 +526,8 @@ def batch_extras(dev, nmat=256, ks=(1, 4, 16)):
         C.free()
     del csrs
     for dt, tdt in (("float64", torch.float64), ("float32", torch.float32)):
+        if dt not in dtypes:
+            continue
         log(f"batch: autotune + convert {dt}")
         Ms, shapes = [], {}
         for A in mats:
@@ -589,7 +593,8 @@ def batch_extras(dev, nmat=256, ks=(1, 4, 16)):
                 "schedule": "tuned" if use_tuned else "default",
                 "tuned_tile_caps": hist, "tuning_s": round(tune_s, 2),
                 "speedup_vs_plain_fp64_csr": round(plain / us, 2),
-                "speedup_vs_plain_fp64_spc5": round(k * res["plain_fp64_spc5_us_per_vector"] / us, 2),
+                "speedup_vs_plain_fp64_spc5": (round(k * res["plain_fp64_spc5_us_per_vector"] / us, 2)
+                                               if "plain_fp64_spc5_us_per_vector" in res else None),
                 "max_rel_l2_all_matrices": max(errs)}
             del Xs, Ys, Yh
         B.free()
@@ -681,7 +686,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="fem")
+    ap.add_argument("--workload", default="fem", help="fem, laplacian, random or zipf")
+    ap.add_argument("--dtype", default="float64",
+                    help="value type of the timed product (float64; float32 for profiling)")
+    ap.add_argument("--batch-ks", default="1,4,16", help="right-hand sides of the batch legs")
+    ap.add_argument("--batch-dtypes", default="float64,float32")
     ap.add_argument("--no-extras", action="store_true", help="only the primary format")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-passes", type=int, default=5)
@@ -696,7 +705,7 @@ def main():
                          "rocprofv3 --pmc counter files and exit")
     args = ap.parse_args()
     if args.traffic_from:
-        traffic_write(args.traffic_from[0], args.traffic_from[1], args.workload)
+        traffic_write(args.traffic_from[0], args.traffic_from[1], args.workload, args.dtype)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: this library has no multi-GPU path, so "
@@ -712,16 +721,18 @@ def main():
 
     dev = torch.device("cuda:0")
     log(f"generating workload {args.workload}")
-    A, rc, tag = make_workload(args.workload)
-    x = torch.from_numpy(A.x).to(dev)
+    A, rc, tag = make_workload(args.workload, args.dtype)
+    tdt = torch.float64 if args.dtype == "float64" else torch.float32
+    x = torch.from_numpy(A.x).to(dev, tdt)
     yref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
     flops = 2.0 * A.nnz
+    gate = 1e-14 if args.dtype == "float64" else 1e-6
 
     def measure(M, steps, warmup, nbytes, flush=None):
         """Mean launch time from one event pair around `steps` back-to-back
         launches; with a cache flush between launches, from an event pair
         around every launch (the flush stays outside the events)."""
-        y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+        y = torch.empty(A.nrows, dtype=tdt, device=dev)
         if flush is None:
             wall, avg = time_region(lambda: M.spmv(x, y), steps, warmup)
             # per-launch event pairs on a few more launches: the fastest launch
@@ -729,7 +740,7 @@ def main():
         else:
             wall, ms = time_launches(lambda: M.spmv(x, y), steps, warmup, flush)
             avg = float(np.mean(ms))
-        err = oracle.rel_l2(y.cpu().numpy(), yref)
+        err = oracle.rel_l2(y.cpu().double().numpy(), yref)
         return {"gflops": round(flops / (avg * 1e-3) / 1e9, 2),
                 "launch_us": round(avg * 1e3, 2), "min_launch_us": round(min(ms) * 1e3, 2),
                 "gbs": round(nbytes / (avg * 1e-3) / 1e9, 1),
@@ -744,11 +755,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     log(f"converting to beta{rc}")
-    M = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, *rc)
+    M = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, *rc, args.dtype)
     nbytes = M.info.spmv_bytes
     log(f"timing {args.steps} steps after {args.warmup} warmup")
     prim, wall, avg_ms = measure(M, args.steps, args.warmup, nbytes)
-    if not prim["rel_l2"] <= 1e-14:
+    if not prim["rel_l2"] <= gate:
         raise SystemExit(f"parity failure: rel L2 {prim['rel_l2']}")
     avg_s = avg_ms * 1e-3
     achieved = nbytes / avg_s / 1e9
@@ -763,7 +774,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.dtype == "float64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"{tag} beta({rc[0]},{rc[1]})", "nrows": A.nrows,
                    "ncols": A.ncols, "nnz": A.nnz, "r": rc[0], "c": rc[1],
@@ -778,6 +789,9 @@ def main():
     }
     extras = set() if args.no_extras else {"kernels", "formats", "csr", "flushed", "other",
                                            "backward", "batch", "ablation"} - skip
+    if args.dtype != "float64" and extras & {"kernels", "formats", "csr", "flushed"}:
+        raise SystemExit("a float32 timed product is for profiling: skip kernels, formats, csr "
+                         "and flushed")
     if "kernels" in extras:
         prim["kernel"] = M.kernel
         kern = {M.kernel: prim}
@@ -800,7 +814,7 @@ def main():
                 continue
             log(f"timing beta({r},{c})")
             M2 = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c)
-            formats[f"beta({r},{c})"] = measure(M2, 50, 5, M2.info.spmv_bytes)[0]
+            formats[f"beta({r},{c})"] = measure(M2, 100, 30, M2.info.spmv_bytes)[0]
             formats[f"beta({r},{c})"]["fill"] = round(M2.info.fill, 4)
             formats[f"beta({r},{c})"]["kernel"] = M2.kernel
             M2.free()
@@ -812,7 +826,7 @@ def main():
         for (r, c) in [rc, (4, 8), (1, 16), (2, 16), (4, 16), (8, 16)]:
             log(f"timing float32 beta({r},{c})")
             M3 = spc5.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, r, c, "float32")
-            us32 = time_region(lambda: M3.spmv(x32, y32), 50, 5)[1] * 1e3
+            us32 = time_region(lambda: M3.spmv(x32, y32), 100, 30)[1] * 1e3
             formats[f"float32 beta({r},{c})"] = {
                 "gflops": round(flops / us32 / 1e3, 2), "launch_us": round(us32, 2),
                 "gbs": round(M3.info.spmv_bytes / us32 / 1e3, 1),
@@ -857,7 +871,9 @@ def main():
     if "backward" in extras:
         out["backward"] = backward_extras(dev)
     if "batch" in extras:
-        out["batch"] = batch_extras(dev, args.batch_mats)
+        out["batch"] = batch_extras(dev, args.batch_mats,
+                                    tuple(int(k) for k in args.batch_ks.split(",")),
+                                    tuple(args.batch_dtypes.split(",")))
     if "ablation" in extras:
         if A_lap is None:
             from paper_2307_14774_amd import workloads as W

@@ -289,7 +289,7 @@ void spc5_batch_free(spc5_batch *B);
  * panels, of one work item's tile.  Value-mode batches (every matrix
  * beta(1,c)) cut the matrix's batch schedule into tiles of at most this many
  * panels (besides the value and block caps); the work-queue kernel uses it as
- * the SpMM tile width.  0 (the default) restores the built-in choice: as many
+ * the SpMM tile width (at most 64 panels there).  0 (the default) restores the built-in choice: as many
  * panels as a tile holds, or the matrix's sweep tile width.  1..256.  Takes
  * effect at spc5_batch_create.  Errors: SPC5_EINVAL (NULL A, cap out of
  * range). */

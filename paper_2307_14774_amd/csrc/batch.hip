@@ -746,7 +746,8 @@ int spc5_batch_set_operands(spc5_batch *B, int nrhs, const void *const *X, void 
         d.npanels = A->npanels;
         d.nrows = A->nrows;
         d.shape = A->r * 100 + (A->c <= 4 ? 4 : (A->c <= 8 ? 8 : 16));
-        const int want = A->batch_ppt ? A->batch_ppt : A->ppt;
+        // a wavefront tile holds at most 64 panels (one lane per panel end)
+        const int want = A->batch_ppt ? std::min(A->batch_ppt, 64) : A->ppt;
         d.ppt = std::max(1, std::min(want, kSpmmTile / (A->r * K)));
         d.tile0 = tile0;
         const int64_t nt = (A->npanels + d.ppt - 1) / d.ppt;

@@ -262,9 +262,24 @@ __global__ void k_zero(uint32_t *p, int64_t nwords, uint8_t *tail, int ntail) {
     if (i < ntail) tail[i] = 0;
 }
 
+// 16 bytes per thread over a 16-byte aligned range.
+__global__ void k_zero16(uint4 *p, int64_t n16) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n16) p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 hipError_t zero_fill(void *p, int64_t n, int elem_bytes, hipStream_t s) {
-    const int64_t bytes = n * elem_bytes;
+    int64_t bytes = n * elem_bytes;
     if (bytes <= 0) return hipSuccess;
+    if (((uintptr_t)p & 15) == 0 && bytes >= 4096) {
+        // the 16-byte aligned bulk, then the rest word by word
+        const int64_t n16 = bytes / 16;
+        hipLaunchKernelGGL(k_zero16, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, s,
+                           (uint4 *)p, n16);
+        p = (uint8_t *)p + n16 * 16;
+        bytes -= n16 * 16;
+        if (bytes == 0) return hipGetLastError();
+    }
     const int64_t nwords = bytes / 4;
     const int ntail = (int)(bytes - nwords * 4);
     const int64_t work = nwords > ntail ? nwords : ntail;

@@ -231,8 +231,11 @@ __device__ __forceinline__ SegSum<T> seg_join(SegSum<T> a, SegSum<T> b) {
 // that started in an earlier bucket goes to head[b], the segment of a row
 // that starts here and goes on goes to tail[b] (k_edge_fixup adds them).
 // Empty rows keep the zero written before the pass.
+// FP32: two workgroups per compute unit (64 KiB of LDS each) need 8 waves
+// per SIMD, i.e. at most 64 VGPRs.
 template <typename T>
-__global__ __launch_bounds__(kMoveThreads) void k_bucket_sums(
+__global__ __launch_bounds__(kMoveThreads)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
     int64_t n, int nheads, const uint16_t *__restrict__ src, const T *__restrict__ stage,
     const int32_t *__restrict__ hoff, const int32_t *__restrict__ hpos,
     const int32_t *__restrict__ hrow, T *__restrict__ head, T *__restrict__ tail,
@@ -269,9 +272,10 @@ __global__ __launch_bounds__(kMoveThreads) void k_bucket_sums(
         w0 = sp[0];
         w1 = sp[1];
     }
-    int hp[kSumPer];
+    constexpr int kHp = 4;              // heads per thread read up front
+    int hp[kHp];
 #pragma unroll
-    for (int i = 0; i < kSumPer; ++i) {
+    for (int i = 0; i < kHp; ++i) {
         const int k = h0 + th + i * kMoveThreads;
         hp[i] = k < h1 ? hpos[k] : -1;
     }
@@ -283,11 +287,15 @@ __global__ __launch_bounds__(kMoveThreads) void k_bucket_sums(
     for (int k = th; k < W / 32 + 1; k += kMoveThreads) flags[k] = 0u;
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kSumPer; ++i) {
+    for (int i = 0; i < kHp; ++i) {
         if (hp[i] >= 0) {
             const int pos = hp[i] - (int)q0;
             atomicOr(&flags[pos >> 5], 1u << (pos & 31));
         }
+    }
+    for (int k = h0 + th + kHp * kMoveThreads; k < h1; k += kMoveThreads) {
+        const int pos = hpos[k] - (int)q0;
+        atomicOr(&flags[pos >> 5], 1u << (pos & 31));
     }
     __syncthreads();
     // products of this thread's positions and their head bits (bit 16: the
@@ -349,11 +357,13 @@ __global__ __launch_bounds__(kMoveThreads) void k_bucket_sums(
     heads_before += cex;
     if (t0 >= m) return;
     // rows of the segments ending in this thread: the open segment's head
-    // (h0-1: an earlier bucket's) and this thread's heads, read together
+    // (h0-1: an earlier bucket's) and this thread's first heads, read
+    // together; further heads are read when their segment ends
     const int kin = h0 + heads_before - 1;
-    int rows[kSumPer + 1];
+    constexpr int kRows = 4;
+    int rows[kRows];
 #pragma unroll
-    for (int i = 0; i <= kSumPer; ++i) {
+    for (int i = 0; i < kRows; ++i) {
         const int k = kin + i;
         rows[i] = i <= cnt && k >= h0 ? hrow[k] : -1;
     }
@@ -380,8 +390,14 @@ __global__ __launch_bounds__(kMoveThreads) void k_bucket_sums(
                     // position and the next row does not start right after it
                     const bool after = last && q0 + m < n &&
                                        (k + 1 >= nheads || hpos[k + 1] != (int)(q0 + m));
-                    if (after) tail[b] = run;
-                    else xbar[rows[kk]] = run;
+                    if (after) {
+                        tail[b] = run;
+                    } else {
+                        int j = kk < kRows ? rows[0] : hrow[k];
+#pragma unroll
+                        for (int q = 1; q < kRows; ++q) j = kk == q ? rows[q] : j;
+                        xbar[j] = run;
+                    }
                 }
             }
         }

@@ -262,3 +262,39 @@ def test_autotune_shape_and_schedule(dev):
     y = M.spmv(torch.tensor(A.x, device=dev)).cpu().numpy()
     ref = oracle.csr_spmv(A.rowptr, A.colidx, A.values, A.x)
     assert oracle.rel_l2(y, ref) <= 1e-14
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("k", [1, 4, 16])
+def test_batch_per_matrix_schedules(dtype, k, dev):
+    """Per-matrix batch tile caps (spc5_set_batch_schedule, as the autotuner
+    sets them), on the value-mode batch (hub rows split into pieces) and on
+    the work-queue batch: every matrix against the FP64 oracle; the tuner
+    keeps one of its candidates per matrix."""
+    from paper_2307_14774_amd import autotune
+    S = spc5()
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    gate = 1e-14 if dtype == "float64" else 1e-6
+    rng = np.random.default_rng(300 + k)
+    for label, mats_h, shapes in (("value mode", R1, R1_SHAPES), ("work queue", BATCH, BATCH_SHAPES)):
+        say(f"per-matrix batch schedules {label} {dtype} k={k}")
+        mats = [S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols,
+                                      *shapes[m % len(shapes)], dtype) for m, A in enumerate(mats_h)]
+        caps = [(0, 128, 64, 32, 8, 1)[m % 6] for m in range(len(mats))]
+        for M, cp in zip(mats, caps):
+            M.set_batch_schedule(cp)
+        Xh = [rng.uniform(-1, 1, (A.ncols, k)) for A in mats_h]
+        B = S.Spc5Batch(mats)
+        Ys = B.spmm([torch.tensor(X, dtype=tdt, device=dev) for X in Xh])
+        torch.cuda.synchronize()
+        for m, A in enumerate(mats_h):
+            v = A.values if dtype == "float64" else A.values.astype(np.float32).astype(np.float64)
+            X = Xh[m] if dtype == "float64" else Xh[m].astype(np.float32).astype(np.float64)
+            ref = oracle.csr_spmm(A.rowptr, A.colidx, v, X)
+            assert oracle.rel_l2(Ys[m].cpu().double().numpy(), ref) <= gate, (label, m, caps[m])
+        B.free()
+        if label == "value mode":
+            chosen = autotune.tune_batch(mats[:4], k)
+            assert all(c in autotune.BATCH_PPT for c in chosen)
+    with pytest.raises(S.Spc5Error):
+        mats[0].set_batch_schedule(257)

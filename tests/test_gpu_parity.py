@@ -449,6 +449,35 @@ def test_staged_variants(A, rc, variant, dtype, dev):
     assert M.info.variant == 0
 
 
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_variants_on_16k_value_tiles(dtype, dev):
+    """A matrix large and dense enough for 16 KiB value tiles (FEM 40^3 x 3,
+    15.5 M nonzeros): switching to a variant refits the schedule to the
+    variants' block cap, switching back restores the default; every product
+    against the oracle."""
+    A = W.fem_3d(40, seed=41)
+    S = spc5()
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    gate = 1e-14 if dtype == "float64" else 1e-6
+    v = A.values if dtype == "float64" else A.values.astype(np.float32).astype(np.float64)
+    xr = A.x if dtype == "float64" else A.x.astype(np.float32).astype(np.float64)
+    ref = oracle.csr_spmv(A.rowptr, A.colidx, v, xr)
+    x = to_dev(A.x, dev, tdt)
+    say(f"variants on 16 KiB tiles {dtype}")
+    for rc in [(4, 4), (2, 4), (8, 8)]:
+        M = S.Spc5Matrix.from_csr(A.rowptr, A.colidx, A.values, A.ncols, *rc, dtype)
+        y0 = M.spmv(x).cpu().double().numpy()
+        assert oracle.rel_l2(y0, ref) <= gate
+        for var in [(False, False, True), (True, False, False), (False, True, False)]:
+            M.set_variant(*var)
+            assert oracle.rel_l2(M.spmv(x).cpu().double().numpy(), ref) <= gate, (rc, var)
+            M.set_schedule("staged")       # rebuilt with the variant kept
+            assert oracle.rel_l2(M.spmv(x).cpu().double().numpy(), ref) <= gate, (rc, var)
+        M.set_variant()
+        assert np.array_equal(M.spmv(x).cpu().double().numpy(), y0)
+        M.free()
+
+
 def test_variant_errors(dev):
     S = spc5()
     A = W.random_sparse(50, 40, 0.1, seed=28)
