@@ -51,8 +51,9 @@ struct spc5_matrix {
                                    // offsets from tr_cbase[chunk], or int32 when it is NULL
     int32_t *tr_cbase = nullptr;   // [nbuckets] base row of every chunk of A
     int32_t *tr_hoff = nullptr;    // [nbuckets+1] first nonempty A^T row of each bucket
-    int32_t *tr_hpos = nullptr;    // [nheads] first position of each nonempty A^T row
-    int32_t *tr_hrow = nullptr;    // [nheads] its row index
+    uint32_t *tr_hbits = nullptr;  // [nbuckets*W/32+1] bit q: position q starts a row of A^T
+    int32_t *tr_hrow = nullptr;    // [nheads] row index of each nonempty A^T row
+    int32_t *tr_rlo = nullptr;     // [nbuckets+1] first row owned by each bucket
     int64_t tr_nheads = 0;
     int32_t *tr_edge_rows = nullptr;   // [3*nedge] (row, first bucket, last bucket)
     int64_t tr_nedge = 0, tr_nbuckets = 0;

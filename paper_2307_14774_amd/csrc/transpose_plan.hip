@@ -22,17 +22,19 @@
 //     packed order, where ybar is read row after row), x_bar[j] is the sum
 //     of the p's of A^T's row j, i.e. a segmented sum of p in A^T's CSR
 //     order.  A single gather p[order[q]] would read one scattered word per
-//     cache line, so A^T's CSR order is cut into buckets of W = 16384
-//     positions (one LDS window), A's values get staging slots grouped by
-//     bucket (inside a bucket: A's packed order), and two passes run, each
-//     through LDS: pass 1 loads a contiguous chunk of W values of A, forms
-//     their products and writes them out in slot order (one contiguous run
-//     per bucket); pass 2 loads one bucket's slots, reads them in A^T's
-//     order through 16-bit local indices and sums each row's run with a
-//     workgroup segmented scan.  A row inside one bucket is stored there;
-//     a row cut by bucket edges leaves its bucket-edge partial sums, added
-//     in bucket order by a fixup.  Every global access is contiguous, there
-//     are no atomics, and the result is reproducible bit for bit.
+//     cache line, so A^T's CSR order is cut into buckets of 8192 positions
+//     (one LDS window), A's values get staging slots grouped by bucket
+//     (inside a bucket: A's packed order), and two passes run, each through
+//     LDS: pass 1 loads a contiguous chunk of 16384 values of A, forms their
+//     products and writes them out in slot order (one contiguous run per
+//     bucket); pass 2 loads one bucket's slots, reads them in A^T's order
+//     through 16-bit local indices and sums each row's run with a workgroup
+//     segmented scan.  A row inside one bucket is stored there; a row cut by
+//     bucket edges leaves its bucket-edge partial sums, added in bucket
+//     order by a fixup.  Every global access is contiguous, there are no
+//     atomics, and the result is reproducible bit for bit.  (Chunks are
+//     larger than buckets: longer runs per bucket in pass 1; smaller
+//     windows, so more workgroups resident per compute unit, in pass 2.)
 #include "spc5_internal.h"
 #include "wave.h"
 
@@ -94,8 +96,10 @@ __global__ void k_gather_csr(int64_t nnz, const int32_t *__restrict__ idx,
 
 // Values per LDS window of the two-pass value move (128 KiB in FP64, 64 KiB
 // in FP32: two workgroups per compute unit), and threads per workgroup.
-constexpr int kMoveValues = 16384;
-constexpr int kMoveThreads = 1024;
+constexpr int kChunkValues = 16384;   // pass 1: values of A per workgroup
+constexpr int kChunkThreads = 1024;
+constexpr int kBucketValues = 8192;   // pass 2: positions of A^T per workgroup
+constexpr int kBucketThreads = 512;
 
 // key[perm[q]] = bucket of q: for every packed value of A, the bucket of its
 // position in A^T.
@@ -136,34 +140,41 @@ __global__ void k_chunk_lists(int64_t nnz, int64_t w, const int32_t *__restrict_
 
 // Pass 1: workgroup c loads values [c*W, c*W + m) of A into LDS, each
 // multiplied by ybar at its row, then writes stage[gpos[j]] = win[lidx[j]]
-// over its slot-ordered list.  Each thread handles pairs of consecutive
-// list entries (8-byte slot and 4-byte local-index loads).  Rows come as
-// 16-bit offsets from the chunk's base row (R16) or as full indices.
+// over its slot-ordered list.  The products are formed in pairs of
+// consecutive values (4-byte loads of two 16-bit row offsets); the stores
+// go one list position per lane, consecutive lanes on consecutive positions,
+// so that one store instruction covers whole runs of consecutive slots (a
+// bucket's run from one chunk is a few dozen bytes).  Rows come as 16-bit
+// offsets from the chunk's base row (R16) or as full indices.
 template <typename T, bool R16>
-__global__ __launch_bounds__(kMoveThreads) void k_move_products(
+__global__ __launch_bounds__(kChunkThreads) void k_move_products(
     int64_t n, const uint16_t *__restrict__ lidx, const int32_t *__restrict__ gpos,
     const T *__restrict__ in, const void *__restrict__ arow, const int32_t *__restrict__ cbase,
     const T *__restrict__ ybar, T *__restrict__ stage) {
-    constexpr int W = kMoveValues;
-    constexpr int P = W / (2 * kMoveThreads);
+    constexpr int W = kChunkValues;
+    constexpr int P = W / (2 * kChunkThreads);     // value pairs per thread
+    constexpr int Q = W / kChunkThreads;           // list positions per thread
     __shared__ T win[W];
-    const int64_t c0 = (int64_t)blockIdx.x * W;
+    const int64_t cb = blockIdx.x;
+    const int64_t c0 = cb * W;
     const int m = (int)min((int64_t)W, n - c0);
     const int th = threadIdx.x;
-    uint64_t g[P];
-    uint32_t l[P];
+    // the list's slots and local indices: independent of the products, read
+    // first
+    int32_t g[Q];
+    uint32_t l[Q];
 #pragma unroll
-    for (int e = 0; e < P; ++e) {
-        const int k = 2 * (th + e * kMoveThreads);
-        g[e] = k < m ? *(const uint64_t *)(gpos + c0 + k) : 0;
-        l[e] = k < m ? *(const uint32_t *)(lidx + c0 + k) : 0;
+    for (int e = 0; e < Q; ++e) {
+        const int j = th + e * kChunkThreads;
+        g[e] = j < m ? gpos[c0 + j] : 0;
+        l[e] = j < m ? (uint32_t)lidx[c0 + j] : 0u;
     }
     if constexpr (R16) {
         const uint16_t *rr = (const uint16_t *)arow;
-        const int rb = cbase[blockIdx.x];
+        const int rb = cbase[cb];
 #pragma unroll
         for (int e = 0; e < P; ++e) {
-            const int k = 2 * (th + e * kMoveThreads);
+            const int k = 2 * (th + e * kChunkThreads);
             const uint32_t rp = k < m ? *(const uint32_t *)(rr + c0 + k) : 0u;
             if (k < m) win[k] = in[c0 + k] * ybar[rb + (int)(rp & 0xffffu)];
             if (k + 1 < m) win[k + 1] = in[c0 + k + 1] * ybar[rb + (int)(rp >> 16)];
@@ -172,17 +183,16 @@ __global__ __launch_bounds__(kMoveThreads) void k_move_products(
         const int32_t *rr = (const int32_t *)arow;
 #pragma unroll
         for (int e = 0; e < P; ++e) {
-            const int k = 2 * (th + e * kMoveThreads);
+            const int k = 2 * (th + e * kChunkThreads);
             if (k < m) win[k] = in[c0 + k] * ybar[rr[c0 + k]];
             if (k + 1 < m) win[k + 1] = in[c0 + k + 1] * ybar[rr[c0 + k + 1]];
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < P; ++e) {
-        const int k = 2 * (th + e * kMoveThreads);
-        if (k < m) stage[(uint32_t)g[e]] = win[l[e] & 0xffffu];
-        if (k + 1 < m) stage[(uint32_t)(g[e] >> 32)] = win[l[e] >> 16];
+    for (int e = 0; e < Q; ++e) {
+        const int j = th + e * kChunkThreads;
+        if (j < m) stage[(uint32_t)g[e]] = win[l[e]];
     }
 }
 
@@ -206,7 +216,7 @@ __global__ void k_rows16(int64_t nnz, int64_t w, const int32_t *__restrict__ row
 }
 
 // Positions of a bucket per thread in pass 2 (consecutive).
-constexpr int kSumPer = kMoveValues / kMoveThreads;
+constexpr int kSumPer = kBucketValues / kBucketThreads;
 static_assert(kSumPer == 16, "two 16-byte loads of 16-bit indices per thread");
 
 // Segmented-sum operator: (head seen, sum since the last head).
@@ -223,29 +233,34 @@ __device__ __forceinline__ SegSum<T> seg_join(SegSum<T> a, SegSum<T> b) {
 
 // Pass 2: workgroup b loads bucket b's slots [b*W, b*W + m) into LDS.
 // Thread t owns positions t*16 .. t*16+15 of the bucket in A^T's CSR order;
-// position q's product is win[src[q]].  The heads of the bucket (first
-// positions of the nonempty rows that start in it, hpos[hoff[b]..hoff[b+1]),
-// rows hrow[...]) are flagged in LDS; a workgroup segmented scan carries each
-// row's running sum, and the number of heads, across threads.  A row that
-// starts and ends in the bucket is stored in xbar; the segment of the row
-// that started in an earlier bucket goes to head[b], the segment of a row
-// that starts here and goes on goes to tail[b] (k_edge_fixup adds them).
-// Empty rows keep the zero written before the pass.
+// position q's product is win[src[q]].  The heads (first positions of the
+// nonempty rows of A^T) come from a bitmap over all positions, read straight
+// from memory; a workgroup segmented scan carries each row's running sum,
+// and the number of heads, across threads.  The sum of a row that starts
+// and ends in the bucket goes to LDS, at its head's number inside the
+// bucket, and all of them are stored to x_bar in one coalesced sweep at the
+// end (rows from hrow, read up front).  The segment of a row that started in
+// an earlier bucket goes to head[b], that of a row that starts here and goes
+// on to tail[b] (k_edge_fixup adds them).  The workgroup first stores zeros
+// to the rows it owns, [rlo[b], rlo[b+1]): those whose first position lies
+// in the bucket (for the last bucket also the empty rows at the end), so
+// empty rows need no fill of their own; a wait for those stores before the
+// first barrier puts them ahead of the sums.
 // FP32: two workgroups per compute unit (64 KiB of LDS each) need 8 waves
 // per SIMD, i.e. at most 64 VGPRs.
 template <typename T>
-__global__ __launch_bounds__(kMoveThreads)
+__global__ __launch_bounds__(kBucketThreads)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
-    int64_t n, int nheads, const uint16_t *__restrict__ src, const T *__restrict__ stage,
-    const int32_t *__restrict__ hoff, const int32_t *__restrict__ hpos,
-    const int32_t *__restrict__ hrow, T *__restrict__ head, T *__restrict__ tail,
-    T *__restrict__ xbar) {
-    constexpr int W = kMoveValues;
-    constexpr int NWV = kMoveThreads / kWave;
+    int64_t n, const uint16_t *__restrict__ src, const T *__restrict__ stage,
+    const uint32_t *__restrict__ hbits, const int32_t *__restrict__ hoff,
+    const int32_t *__restrict__ hrow, const int32_t *__restrict__ rlo, T *__restrict__ head,
+    T *__restrict__ tail, T *__restrict__ xbar) {
+    constexpr int W = kBucketValues;
+    constexpr int NWV = kBucketThreads / kWave;
     constexpr int VPL = 16 / (int)sizeof(T);            // values per 16-byte load
     constexpr int NLD = kSumPer / VPL;                   // loads per thread
+    constexpr int kHr = 2;                               // head rows per thread read up front
     __shared__ T win[W];
-    __shared__ uint32_t flags[W / 32 + 1];
     __shared__ int s_f[NWV], s_c[NWV];
     __shared__ T s_v[NWV];
     const int b = blockIdx.x;
@@ -254,11 +269,21 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
     const int th = threadIdx.x, lane = lane_id(), wv = th / kWave;
     const int t0 = th * kSumPer;
     const int h0 = hoff[b], h1 = hoff[b + 1];
-    // every global read of the pass that does not depend on the scan, issued
-    // together: the bucket's slots (16 consecutive values per thread; the
-    // staging array is padded past its end), this thread's 16 positions'
-    // slot indices, and the first positions of up to 16 of the bucket's
-    // heads (a bucket has at most W = 16 * kMoveThreads of them)
+    // the last head's row goes on past the bucket when the position after
+    // the bucket exists and starts no row
+    const int64_t qe = q0 + m;
+    const bool has_tail =
+        h1 > h0 && qe < n && !((hbits[qe >> 5] >> (unsigned)(qe & 31)) & 1u);
+    const int nint = h1 - h0 - (has_tail ? 1 : 0);      // rows stored from LDS
+    // zeros to the owned rows, first
+    {
+        const int rl0 = rlo[b], rl1 = rlo[b + 1];
+        for (int j = rl0 + th; j < rl1; j += kBucketThreads) xbar[j] = T(0);
+    }
+    // the global reads of the products, issued together: the bucket's slots
+    // (16 consecutive values per thread; the staging array is padded past
+    // its end), this thread's 16 slot indices and its 17 head bits (bit 16:
+    // the next thread's first position, or the next bucket's)
     typedef unsigned v4 __attribute__((ext_vector_type(4)));
     v4 r[NLD];
     {
@@ -272,34 +297,19 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
         w0 = sp[0];
         w1 = sp[1];
     }
-    constexpr int kHp = 4;              // heads per thread read up front
-    int hp[kHp];
-#pragma unroll
-    for (int i = 0; i < kHp; ++i) {
-        const int k = h0 + th + i * kMoveThreads;
-        hp[i] = k < h1 ? hpos[k] : -1;
-    }
+    const int64_t pw = (q0 + t0) >> 5;                   // t0 & 31 is 0 or 16
+    const uint32_t bw0 = hbits[pw];
+    const uint32_t bw1 = (t0 & 31) ? hbits[pw + 1] : 0u;
     {
         v4 *wp = (v4 *)(win + t0);
 #pragma unroll
         for (int g = 0; g < NLD; ++g) wp[g] = r[g];
     }
-    for (int k = th; k < W / 32 + 1; k += kMoveThreads) flags[k] = 0u;
+    // the zero stores complete before the barrier, so that the sums other
+    // waves store to the same rows after it land later
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kHp; ++i) {
-        if (hp[i] >= 0) {
-            const int pos = hp[i] - (int)q0;
-            atomicOr(&flags[pos >> 5], 1u << (pos & 31));
-        }
-    }
-    for (int k = h0 + th + kHp * kMoveThreads; k < h1; k += kMoveThreads) {
-        const int pos = hpos[k] - (int)q0;
-        atomicOr(&flags[pos >> 5], 1u << (pos & 31));
-    }
-    __syncthreads();
-    // products of this thread's positions and their head bits (bit 16: the
-    // next thread's first position)
+    // products of this thread's positions and their head bits
     T p[kSumPer];
     {
         const unsigned wd[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
@@ -309,8 +319,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
             p[i] = t0 + i < m ? win[idx] : T(0);
         }
     }
-    const uint64_t fw = (uint64_t)flags[t0 >> 5] | ((uint64_t)flags[(t0 >> 5) + 1] << 32);
-    const unsigned hb = (unsigned)(fw >> (t0 & 31)) & 0x1ffffu;
+    // positions at or past n carry no head bits (the bitmap is zero there)
+    const unsigned hb = (t0 & 31) ? ((bw0 >> 16) | ((bw1 & 1u) << 16)) : (bw0 & 0x1ffffu);
     // thread aggregate: (head seen, open segment's sum), head count
     SegSum<T> agg = {0, T(0)};
 #pragma unroll
@@ -346,7 +356,16 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
         exw = {0, T(0)};
         cex = 0;
     }
+    // this barrier also ends every read of the window: from here on it
+    // holds the rows' sums
     __syncthreads();
+    // rows of up to kHr of the bucket's heads, read while the walk runs
+    int hr[kHr];
+#pragma unroll
+    for (int i = 0; i < kHr; ++i) {
+        const int u = th + i * kBucketThreads;
+        hr[i] = u < nint ? hrow[h0 + u] : 0;
+    }
     SegSum<T> carry = {0, T(0)};
     int heads_before = 0;
     for (int w2 = 0; w2 < wv; ++w2) {
@@ -355,53 +374,39 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
     }
     carry = seg_join(carry, exw);
     heads_before += cex;
-    if (t0 >= m) return;
-    // rows of the segments ending in this thread: the open segment's head
-    // (h0-1: an earlier bucket's) and this thread's first heads, read
-    // together; further heads are read when their segment ends
-    const int kin = h0 + heads_before - 1;
-    constexpr int kRows = 4;
-    int rows[kRows];
-#pragma unroll
-    for (int i = 0; i < kRows; ++i) {
-        const int k = kin + i;
-        rows[i] = i <= cnt && k >= h0 ? hrow[k] : -1;
-    }
     // walk the positions; a segment ends at e when e+1 is a head or e is the
-    // bucket's last position
+    // bucket's last position.  lh: the segment's head number in the bucket
+    // (-1: the row started in an earlier bucket)
     T run = carry.v;
-    int kk = 0;                         // heads of this thread passed
+    int lh = heads_before - 1;
 #pragma unroll
     for (int i = 0; i < kSumPer; ++i) {
         const int e = t0 + i;
         if (e < m) {
             if ((hb >> i) & 1u) {
                 run = T(0);
-                ++kk;
+                ++lh;
             }
             run += p[i];
             const bool last = e == m - 1;
             if (last || ((hb >> (i + 1)) & 1u)) {
-                const int k = kin + kk;
-                if (k < h0) {
-                    head[b] = run;              // started in an earlier bucket
-                } else {
-                    // the row goes on past the bucket when this is the last
-                    // position and the next row does not start right after it
-                    const bool after = last && q0 + m < n &&
-                                       (k + 1 >= nheads || hpos[k + 1] != (int)(q0 + m));
-                    if (after) {
-                        tail[b] = run;
-                    } else {
-                        int j = kk < kRows ? rows[0] : hrow[k];
-#pragma unroll
-                        for (int q = 1; q < kRows; ++q) j = kk == q ? rows[q] : j;
-                        xbar[j] = run;
-                    }
-                }
+                if (lh < 0)
+                    head[b] = run;
+                else if (last && has_tail)
+                    tail[b] = run;
+                else
+                    win[lh] = run;
             }
         }
     }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kHr; ++i) {
+        const int u = th + i * kBucketThreads;
+        if (u < nint) xbar[hr[i]] = win[u];
+    }
+    for (int u = th + kHr * kBucketThreads; u < nint; u += kBucketThreads)
+        xbar[hrow[h0 + u]] = win[u];
 }
 
 // Rows of A^T cut by bucket edges: x_bar[j] = tail[bs] + head[bs+1] + ... +
@@ -425,22 +430,21 @@ __global__ __launch_bounds__(256) void k_edge_fixup(int64_t nrows, const int32_t
 template <typename T>
 static hipError_t launch_theta_transpose(const spc5_matrix *A, const T *vals, const T *ybar,
                                          T *xbar, hipStream_t s, T *stage, T *edges) {
-    constexpr int64_t W = kMoveValues;
     const int64_t n = A->nnz;
-    // rows without entries stay zero
-    hipError_t e = zero_fill(xbar, A->ncols, (int)sizeof(T), s);
-    if (e != hipSuccess || n == 0) return e;
-    const unsigned grid = (unsigned)((n + W - 1) / W);
-    T *head = edges, *tail = edges + grid;
+    // no buckets: every row of A^T is empty
+    if (n == 0) return zero_fill(xbar, A->ncols, (int)sizeof(T), s);
+    const unsigned nch = (unsigned)((n + kChunkValues - 1) / kChunkValues);
+    const unsigned nbk = (unsigned)A->tr_nbuckets;
+    T *head = edges, *tail = edges + nbk;
     if (A->tr_cbase)
-        hipLaunchKernelGGL((k_move_products<T, true>), dim3(grid), dim3(kMoveThreads), 0, s, n,
+        hipLaunchKernelGGL((k_move_products<T, true>), dim3(nch), dim3(kChunkThreads), 0, s, n,
                            A->tr_lidx, A->tr_gpos, vals, A->tr_arow, A->tr_cbase, ybar, stage);
     else
-        hipLaunchKernelGGL((k_move_products<T, false>), dim3(grid), dim3(kMoveThreads), 0, s, n,
+        hipLaunchKernelGGL((k_move_products<T, false>), dim3(nch), dim3(kChunkThreads), 0, s, n,
                            A->tr_lidx, A->tr_gpos, vals, A->tr_arow, A->tr_cbase, ybar, stage);
-    hipLaunchKernelGGL(k_bucket_sums<T>, dim3(grid), dim3(kMoveThreads), 0, s, n,
-                       (int)A->tr_nheads, A->tr_src, (const T *)stage, A->tr_hoff, A->tr_hpos,
-                       A->tr_hrow, head, tail, xbar);
+    hipLaunchKernelGGL(k_bucket_sums<T>, dim3(nbk), dim3(kBucketThreads), 0, s, n, A->tr_src,
+                       (const T *)stage, A->tr_hbits, A->tr_hoff, A->tr_hrow, A->tr_rlo, head,
+                       tail, xbar);
     if (A->tr_nedge > 0) {
         const int64_t thr = A->tr_nedge * kWave;
         hipLaunchKernelGGL(k_edge_fixup<T>, dim3((unsigned)((thr + 255) / 256)), dim3(256), 0, s,
@@ -459,7 +463,8 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     int64_t *rowptr_t = nullptr;
     void *val_t = nullptr, *tmp = nullptr;
     spc5_matrix *T = nullptr;
-    int32_t *perm = nullptr, *hoff = nullptr, *hpos = nullptr, *hrow = nullptr;
+    int32_t *perm = nullptr, *hoff = nullptr, *hrow = nullptr, *rlo = nullptr;
+    uint32_t *hbits = nullptr;
     int32_t *cbase = nullptr;
     void *arow = nullptr;
     int32_t *edge_rows = nullptr;
@@ -474,7 +479,8 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
         cleanup();
         free_matrix(T);
         for (void *p : {(void *)perm, (void *)lidx, (void *)src, arow, (void *)hoff,
-                        (void *)hpos, (void *)hrow, (void *)edge_rows, (void *)cbase})
+                        (void *)hbits, (void *)hrow, (void *)rlo, (void *)edge_rows,
+                        (void *)cbase})
             if (p) (void)hipFree(p);
         return st;
     };
@@ -549,8 +555,8 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     // every packed value is kept for pass 1; for pass 2 the first position
     // and the row of every nonempty row of A^T, grouped by bucket, and the
     // rows cut by bucket edges.
-    const int64_t W = kMoveValues;
-    const int64_t nbk = (nnz + W - 1) / W;
+    const int64_t W = kBucketValues, WC = kChunkValues;
+    const int64_t nbk = (nnz + W - 1) / W, nch = (nnz + WC - 1) / WC;
     if ((e = hipMalloc((void **)&perm, nz * 4 + kPad)) != hipSuccess ||
         (e = hipMalloc((void **)&lidx, nz * 2 + kPad)) != hipSuccess ||
         (e = hipMalloc((void **)&src, nz * 2 + kPad)) != hipSuccess ||
@@ -561,12 +567,12 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     if (nnz > 0) {
         int *wide = nullptr;
         int hw = 0;
-        if ((e = hipMalloc((void **)&cbase, (size_t)nbk * 4 + kPad)) != hipSuccess ||
+        if ((e = hipMalloc((void **)&cbase, (size_t)nch * 4 + kPad)) != hipSuccess ||
             (e = hipMalloc((void **)&wide, 4)) != hipSuccess)
             return fail_all(hip_fail(e, "allocating the transpose plan"));
         if ((e = zero_fill(wide, 1, 4, s)) == hipSuccess) {
-            hipLaunchKernelGGL(k_chunk_base, dim3((unsigned)((nbk + 255) / 256)), dim3(256), 0, s,
-                               nnz, W, A->r, row_of, cbase, wide);
+            hipLaunchKernelGGL(k_chunk_base, dim3((unsigned)((nch + 255) / 256)), dim3(256), 0, s,
+                               nnz, WC, A->r, row_of, cbase, wide);
             e = hipMemcpy(&hw, wide, 4, hipMemcpyDeviceToHost);
         }
         (void)hipFree(wide);
@@ -575,7 +581,7 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
             if ((e = hipMalloc(&arow, nz * 2 + kPad)) != hipSuccess)
                 return fail_all(hip_fail(e, "allocating the transpose plan"));
             hipLaunchKernelGGL(k_rows16, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz,
-                               W, row_of, cbase, (uint16_t *)arow);
+                               WC, row_of, cbase, (uint16_t *)arow);
         } else {
             (void)hipFree(cbase);
             cbase = nullptr;
@@ -591,10 +597,16 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
         if ((e = hipMemcpy(rp.data(), rowptr_t, rp.size() * 8, hipMemcpyDeviceToHost)) !=
             hipSuccess)
             return fail_all(hip_fail(e, "reading the rowptr of A^T"));
-        std::vector<int32_t> hp, hr, ho((size_t)nbk + 1, 0), er;
+        // head bitmap over every position of every bucket (zero past nnz,
+        // one spare word), rows of the heads grouped by bucket, the rows
+        // each bucket owns (those starting in it; the trailing empty rows go
+        // to the last bucket), and the rows cut by bucket edges
+        const size_t nwords = (size_t)nbk * (W / 32) + 1;
+        std::vector<uint32_t> hb(nwords, 0u);
+        std::vector<int32_t> hr, ho((size_t)nbk + 1, 0), rl((size_t)nbk + 1, 0), er;
         for (int64_t jj = 0; jj < A->ncols; ++jj) {
             if (rp[jj + 1] == rp[jj]) continue;
-            hp.push_back((int32_t)rp[jj]);
+            hb[(size_t)(rp[jj] >> 5)] |= 1u << (unsigned)(rp[jj] & 31);
             hr.push_back((int32_t)jj);
             ++ho[(size_t)(rp[jj] / W) + 1];
             const int64_t bs = rp[jj] / W, be = (rp[jj + 1] - 1) / W;
@@ -605,32 +617,33 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
             }
         }
         for (int64_t bk = 0; bk < nbk; ++bk) ho[bk + 1] += ho[bk];
-        nheads = (int64_t)hp.size();
+        for (int64_t bk = 1; bk < nbk; ++bk)
+            rl[bk] = (int32_t)(std::lower_bound(rp.begin(), rp.end(), bk * W) - rp.begin());
+        rl[nbk] = (int32_t)A->ncols;
+        nheads = (int64_t)hr.size();
         nedge = (int64_t)er.size() / 3;
-        if ((e = hipMalloc((void **)&hpos, std::max<size_t>(hp.size(), 1) * 4 + kPad)) !=
-                hipSuccess ||
+        if ((e = hipMalloc((void **)&hbits, nwords * 4 + kPad)) != hipSuccess ||
             (e = hipMalloc((void **)&hrow, std::max<size_t>(hr.size(), 1) * 4 + kPad)) !=
                 hipSuccess ||
+            (e = hipMalloc((void **)&rlo, rl.size() * 4 + kPad)) != hipSuccess ||
             (e = hipMalloc((void **)&edge_rows, std::max<size_t>(er.size(), 3) * 4)) !=
                 hipSuccess ||
             (e = hipMemcpy(hoff, ho.data(), ho.size() * 4, hipMemcpyHostToDevice)) !=
                 hipSuccess ||
-            (!hp.empty() &&
-             ((e = hipMemcpy(hpos, hp.data(), hp.size() * 4, hipMemcpyHostToDevice)) !=
-                  hipSuccess ||
-              (e = hipMemcpy(hrow, hr.data(), hr.size() * 4, hipMemcpyHostToDevice)) !=
-                  hipSuccess)) ||
+            (e = hipMemcpy(hbits, hb.data(), nwords * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(rlo, rl.data(), rl.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+            (!hr.empty() &&
+             (e = hipMemcpy(hrow, hr.data(), hr.size() * 4, hipMemcpyHostToDevice)) !=
+                 hipSuccess) ||
             (!er.empty() &&
              (e = hipMemcpy(edge_rows, er.data(), er.size() * 4, hipMemcpyHostToDevice)) !=
                  hipSuccess))
             return fail_all(hip_fail(e, "uploading the bucket tables"));
     }
     if (nnz > 0) {
-        const int64_t w = kMoveValues;
         const unsigned grid = (unsigned)((nnz + 255) / 256);
-        const int64_t nb = (nnz + w - 1) / w;
         unsigned bits = 1;
-        while (bits < 31 && ((int64_t)1 << bits) < nb) ++bits;
+        while (bits < 31 && ((int64_t)1 << bits) < std::max(nbk, nch)) ++bits;
         rocprim::counting_iterator<int32_t> iota(0);
         auto sort = [&](int32_t *keys, int32_t *keys_out, int32_t *vals_out) -> hipError_t {
             size_t need = 0;
@@ -647,17 +660,17 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
                                              (size_t)nnz, 0u, bits, s);
         };
         // order[t] (key_s): the value of A in slot t; slot (col_of) its inverse
-        hipLaunchKernelGGL(k_bucket_keys, dim3(grid), dim3(256), 0, s, nnz, w, idx_s, row_of);
+        hipLaunchKernelGGL(k_bucket_keys, dim3(grid), dim3(256), 0, s, nnz, W, idx_s, row_of);
         if ((e = sort(row_of, col_of, key_s)) != hipSuccess)
             return fail_all(hip_fail(e, "sorting by bucket"));
         hipLaunchKernelGGL(k_invert, dim3(grid), dim3(256), 0, s, nnz, key_s, col_of);
-        hipLaunchKernelGGL(k_bucket_src, dim3(grid), dim3(256), 0, s, nnz, w, col_of, idx_s, src);
+        hipLaunchKernelGGL(k_bucket_src, dim3(grid), dim3(256), 0, s, nnz, W, col_of, idx_s, src);
         // pass 1 lists: slots sorted by chunk (stable, so ascending inside a
         // chunk); gpos (perm's memory) = the slots, lidx = local value index
-        hipLaunchKernelGGL(k_chunk_keys, dim3(grid), dim3(256), 0, s, nnz, w, key_s, row_of);
+        hipLaunchKernelGGL(k_chunk_keys, dim3(grid), dim3(256), 0, s, nnz, WC, key_s, row_of);
         if ((e = sort(row_of, idx_s, perm)) != hipSuccess)
             return fail_all(hip_fail(e, "sorting by chunk"));
-        hipLaunchKernelGGL(k_chunk_lists, dim3(grid), dim3(256), 0, s, nnz, w, key_s, perm, lidx);
+        hipLaunchKernelGGL(k_chunk_lists, dim3(grid), dim3(256), 0, s, nnz, WC, key_s, perm, lidx);
         if ((e = hipGetLastError()) != hipSuccess)
             return fail_all(hip_fail(e, "building the value move"));
     }
@@ -671,8 +684,9 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     A->tr_arow = arow;
     A->tr_cbase = cbase;
     A->tr_hoff = hoff;
-    A->tr_hpos = hpos;
+    A->tr_hbits = hbits;
     A->tr_hrow = hrow;
+    A->tr_rlo = rlo;
     A->tr_nheads = nheads;
     A->tr_edge_rows = edge_rows;
     A->tr_nedge = nedge;

@@ -601,9 +601,10 @@ def exact_nnz_matrix(nnz, seed):
 @pytest.mark.parametrize("trc", [(1, 8), (4, 4)], ids=lambda t: "b%d_%d" % t)
 def test_transpose_plan_value_move(dtype, windows, trc, dev):
     """Caller values theta reach A^T's order in two passes through LDS windows
-    of 16384 values: nnz below one window, exactly one and two windows, and a
-    ragged multi-window tail.  Integer data, so the product is exact and
-    compared bit for bit with the oracle."""
+    (chunks of 16384 values of A, buckets of 8192 positions of A^T): nnz
+    below one window, exactly one and two chunks, and a ragged multi-window
+    tail.  Integer data, so the product is exact and compared bit for bit
+    with the oracle."""
     S = spc5()
     w = 16384
     nnz = int(round(windows * w))
@@ -624,6 +625,63 @@ def test_transpose_plan_value_move(dtype, windows, trc, dev):
     assert np.array_equal(xo, oracle.csr_spmv_t(rowptr, colidx, values, wv, ncols))
     xs = M.transpose(to_dev(wv, dev, tdt), values=to_dev(values, dev, tdt)).cpu().double().numpy()
     assert np.array_equal(xs, xo)
+
+
+def bucket_edge_matrix(seed):
+    """A matrix whose transpose exercises every case of the bucketed value
+    move (buckets of 8192 positions of A^T's CSR order): column 0 empty,
+    column 1 with 40,000 entries (a row of A^T over five buckets, the middle
+    ones without a row start), then 20,000 columns with one entry each
+    (buckets with thousands of row starts, and a row starting exactly on the
+    bucket edge 49,152), then columns of 0..40 entries, and 1,000 empty
+    columns at the end.  Small integer values."""
+    rng = np.random.default_rng(seed)
+    nrows, ncols = 50_000, 30_000
+    counts = np.zeros(ncols, dtype=np.int64)
+    counts[1] = 40_000
+    counts[2:20_002] = 1
+    counts[20_002:ncols - 1000] = rng.integers(0, 41, ncols - 1000 - 20_002)
+    rows, cols = [], []
+    for j in np.nonzero(counts)[0]:
+        rows.append(rng.choice(nrows, size=int(counts[j]), replace=False))
+        cols.append(np.full(int(counts[j]), j))
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    rowptr = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=nrows))]).astype(np.int64)
+    values = rng.integers(-3, 4, len(cols)).astype(np.float64)
+    return rowptr, cols.astype(np.int32), values, ncols
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("rc", [(1, 8), (4, 4)], ids=lambda t: "b%d_%d" % t)
+def test_transpose_values_window_edges(dtype, rc, dev):
+    """Caller values theta through the two-pass move on a transpose with a
+    row over three windows, a window of single-entry rows, rows starting on
+    window edges, and empty rows in front, in between and at the end
+    (written by the pass without a separate fill): exact integer data,
+    bit for bit against the oracle, twice in a row with x_bar first filled
+    with NaN."""
+    S = spc5()
+    rowptr, colidx, values, ncols = bucket_edge_matrix(71)
+    r, c = rc
+    say(f"transpose window edges {dtype} beta{rc} nnz={len(colidx)}")
+    M = S.Spc5Matrix.from_csr(rowptr, colidx, values, ncols, r, c, dtype)
+    M.prepare_transpose(1, 8)
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    rng = np.random.default_rng(72)
+    O = oracle.csr_to_spc5(rowptr, colidx, values, ncols, r, c)
+    for rep in range(2):
+        wv = rng.integers(-4, 5, len(rowptr) - 1).astype(np.float64)
+        theta = rng.integers(-3, 4, O.nnz).astype(np.float64)
+        Ot = oracle.Spc5(**{**O.__dict__, "values": theta})
+        rp, ci, vals = oracle.spc5_to_csr(Ot)
+        xb = torch.full((ncols,), float("nan"), dtype=tdt, device=dev)
+        M.transpose(to_dev(wv, dev, tdt), xb, values=to_dev(theta, dev, tdt))
+        got = xb.cpu().double().numpy()
+        assert np.array_equal(got, oracle.csr_spmv_t(rp, ci, vals, wv, ncols)), rep
+    M.free()
 
 
 @pytest.mark.parametrize("plan", [False, True], ids=["scatter", "plan"])
