@@ -60,8 +60,10 @@ static int stream_nvg(int64_t maxv, int sz) {
 // Rows phase of one staged tile: thread = (panel pl, sub-lane, row i) with S
 // sub-lanes per row (np*R*S <= 256 and S*R <= 64, so the butterfly stays in
 // a wavefront).  Returns the row sum on every sub-lane; `lead` marks the
-// sub-lane that stores it.
-template <typename T, int R, int C, int U, bool SPARSE, int VAR = 0>
+// sub-lane that stores it.  The blocks' x windows sit in LDS column-major,
+// x of column k of block b at s_x[k*XS + b]: the sub-lanes of a row read
+// consecutive blocks, so one read instruction hits consecutive words.
+template <typename T, int R, int C, int U, bool SPARSE, int VAR, int XS>
 __device__ __forceinline__ T tile_rows(int np, int b0, int b1, const int *sbp, const uint8_t *smb,
                                        const int *s_boff, const T *sval, const T *s_x,
                                        const T *s_zero, int &pl_out, int &i_out, bool &lead,
@@ -110,14 +112,14 @@ __device__ __forceinline__ T tile_rows(int np, int b0, int b1, const int *sbp, c
             for (int u = 0; u < U; ++u) {
                 unsigned mm = m[u];
                 int jj = j[u];
-                const T *xb = s_x + tt[u] * C;
+                const T *xb = s_x + tt[u];
                 while (__ballot(mm != 0u)) {
                     const unsigned m1 = mm & (mm - 1u);
                     const bool on0 = mm != 0u, on1 = m1 != 0u;
                     const T *pv0 = on0 ? sval + jj : s_zero;
-                    const T *px0 = on0 ? xb + (__ffs(mm) - 1) : s_zero;
+                    const T *px0 = on0 ? xb + (__ffs(mm) - 1) * XS : s_zero;
                     const T *pv1 = on1 ? sval + jj + 1 : s_zero;
-                    const T *px1 = on1 ? xb + (__ffs(m1) - 1) : s_zero;
+                    const T *px1 = on1 ? xb + (__ffs(m1) - 1) * XS : s_zero;
                     const T v0 = *pv0, x0 = *px0, v1 = *pv1, x1 = *px1;
                     a = fma(v0, x0, a);
                     a = fma(v1, x1, a);
@@ -144,7 +146,7 @@ __device__ __forceinline__ T tile_rows(int np, int b0, int b1, const int *sbp, c
                             *xbuf, on ? (uint32_t)(c0u + k) * (uint32_t)sizeof(T) : kOOB);
                         acc[u] = fma(*pv, xv, acc[u]);
                     } else {
-                        const T *px = on ? s_x + tt[u] * C + k : s_zero;
+                        const T *px = on ? s_x + k * XS + tt[u] : s_zero;
                         acc[u] = fma(*pv, *px, acc[u]);
                     }
                 }
@@ -297,7 +299,7 @@ __attribute__((amdgpu_waves_per_eu(stream_residency<T, R, C, NVG, VAR>()))) void
         if (lane == kWave - 1) s_wsum[wv] = incl;
         if (has) {
 #pragma unroll
-            for (int k = 0; k < C; ++k) s_x[tb * C + k] = xw[k];
+            for (int k = 0; k < C; ++k) s_x[k * BT + tb] = xw[k];
         }
         __syncthreads();
         {
@@ -311,7 +313,7 @@ __attribute__((amdgpu_waves_per_eu(stream_residency<T, R, C, NVG, VAR>()))) void
         // 4. rows and 5. butterfly, then one store per row
         int pl, i;
         bool lead;
-        const T accs = tile_rows<T, R, C, U, SPARSE, VAR>(np, b0, b1, sbp, smb, s_boff, sval,
+        const T accs = tile_rows<T, R, C, U, SPARSE, VAR, BT>(np, b0, b1, sbp, smb, s_boff, sval,
                                                           s_x, s_zero, pl, i, lead, scol, &xbuf,
                                                           s_red);
         if (lead) {
