@@ -252,6 +252,91 @@ struct TileStage {
     }
 };
 
+// Tile stage with the block metadata loaded per block, for r in {2, 4, 8}
+// (the r row masks of a block fill 2, 4, 8 or 16 bytes): thread b loads the
+// anchor and the row masks of the tile's block b straight into registers
+// (zeros past the tile's blocks), so the block's x window can be requested
+// as soon as the tile lands, before anything is copied to LDS.  Values and
+// panel bounds are staged as 16-byte vectors, as in TileStage.
+template <int WB> struct MaskWord;
+template <> struct MaskWord<2> { using type = uint16_t; };
+template <> struct MaskWord<4> { using type = uint32_t; };
+template <> struct MaskWord<8> { using type = uint64_t; };
+template <> struct MaskWord<16> { using type = v4u; };
+
+template <int WB>
+__device__ __forceinline__ typename MaskWord<WB>::type buf_load_word(const Buf &b, uint32_t off) {
+    if constexpr (WB == 2)
+        return (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(b.r, (int)off, 0, 0);
+    else if constexpr (WB == 4)
+        return __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)off, 0, 0);
+    else if constexpr (WB == 8)
+        return __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)off, 0, 0));
+    else
+        return buf_load16(b, off);
+}
+
+template <typename T, int R, int C, int NVG>
+struct BlockStage {
+    using Cfg = StreamCfg<T, R, C, NVG>;
+    static constexpr int WB = R * Cfg::MB;
+    using MW = typename MaskWord<WB>::type;
+    static_assert(WB == 2 || WB == 4 || WB == 8 || WB == 16, "row masks of a block: 2..16 bytes");
+    Range16 qv, qp;
+    RegStage<Cfg::NV> rv;
+    RegStage<Cfg::NP> rp;
+    MW mw;        // this thread's block: its r row masks
+    int cw;       // and its anchor
+
+    // All loads unconditionally (past the tile's range they read zeros): a
+    // fixed count keeps the compiler's in-order load counters exact.
+    __device__ __forceinline__ void issue(int p0, int p1, int b0, int b1, int v0, int v1,
+                                          const T *val, const void *masks, const int32_t *blk_col,
+                                          const int32_t *blk_ptr) {
+        qv = range16(val, (int64_t)v0 * (int64_t)sizeof(T), (int64_t)v1 * (int64_t)sizeof(T));
+        qp = range16(blk_ptr, (int64_t)p0 * 4, (int64_t)(p1 + 1) * 4);
+        const int nb = b1 - b0;
+        const Buf mb = make_buf((const uint8_t *)masks + (int64_t)b0 * WB, (int64_t)nb * WB);
+        const Buf cb = make_buf(blk_col + b0, (int64_t)nb * 4);
+        const uint32_t th = threadIdx.x;
+        TileStage<T, R, C, NVG>::fixed(rv, qv);
+        TileStage<T, R, C, NVG>::fixed(rp, qp);
+        mw = buf_load_word<WB>(mb, th * (uint32_t)WB);
+        cw = (int)__builtin_amdgcn_raw_buffer_load_b32(cb.r, (int)(th * 4u), 0, 0);
+    }
+
+    // Union of the block's row masks (the columns it touches) and its value
+    // count, from the registers.
+    __device__ __forceinline__ void union_count(unsigned &u, int &tot) const {
+        constexpr int FB = 8 * Cfg::MB;                 // bits per row mask
+        constexpr unsigned FM = (1u << FB) - 1u;
+        u = 0;
+        if constexpr (WB <= 8) {
+            const uint64_t w = (uint64_t)mw;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) u |= (unsigned)(w >> (rr * FB)) & FM;
+            tot = __popcll(w);
+        } else {
+            tot = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const unsigned d = mw[q];
+                u |= (d & 0xffffu) | (d >> 16);
+                tot += __popc(d);
+            }
+        }
+    }
+
+    // The block's masks and anchor to LDS (masks of block b at b*WB bytes).
+    __device__ __forceinline__ void commit_block(uint8_t *smask, int *scol, bool has) const {
+        const int th = threadIdx.x;
+        if (has) {
+            *(MW *)(smask + th * WB) = mw;
+            scol[th] = cw;
+        }
+    }
+};
+
 // Row sums of a value-mode tile.  Rows are contiguous value ranges
 // (range(row, vs, ve)).  Every row gets S sub-lanes (S the largest power of
 // two with np*S <= 256, at most 64) that stride its values and meet in a

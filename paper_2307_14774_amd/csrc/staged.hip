@@ -36,6 +36,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
+#include <type_traits>
 #include <vector>
 
 namespace spc5 {
@@ -231,7 +232,10 @@ __attribute__((amdgpu_waves_per_eu(stream_residency<T, R, C, NVG, VAR>()))) void
     int p0 = tile_p[t_begin], p1 = f0 ? p0 + 1 : tile_p[t_begin + 1];
     int b0 = tile_b[t_begin], b1 = tile_b[t_begin + 1];
     int v0 = tile_v[t_begin], v1 = tile_v[t_begin + 1];
-    TileStage<T, R, C, NVG> st;
+    // r in {2, 4, 8}: a block's row masks fill 2..16 bytes, loaded per block
+    constexpr bool PB = R == 2 || R == 4 || R == 8;
+    using Stage = std::conditional_t<PB, BlockStage<T, R, C, NVG>, TileStage<T, R, C, NVG>>;
+    Stage st;
     st.issue(p0, p1, b0, b1, v0, v1, val, masks, blk_col, blk_ptr);
 
     for (int64_t t = t_begin; t < t_end; ++t) {
@@ -242,57 +246,79 @@ __attribute__((amdgpu_waves_per_eu(stream_residency<T, R, C, NVG, VAR>()))) void
         const int q0 = tile_p[tn], q1 = g0 ? q0 + 1 : tile_p[tn + 1];
         const int c0 = tile_b[tn], c1 = tile_b[tn + 1];
         const int w0 = tile_v[tn], w1 = tile_v[tn + 1];
+        const int np = p1 - p0;
+        const int nbt = b1 - b0;
+        const bool has = th < nbt;
+        const int tb = has ? th : 0;
 
-        // 1. land the staged tile in LDS
+        // 1. land the staged tile, and 3. the single x load per block: one
+        // thread per block gathers the whole window x[anchor .. anchor+C) in
+        // 16-byte loads (the buffer range check is per dword, so a window
+        // running past the last column reads zeros there, and blocks whose
+        // rows use no column read nothing), then the next tile's staging
+        // loads are issued, so both are in flight together and waiting for
+        // the gathers does not wait for them (the scheduling barriers keep
+        // the compiler from reordering the groups).  On the last tile the
+        // current tile is re-requested (cache hits): keeping the issue
+        // unconditional keeps the load counters exact on every path.
+        unsigned un;
+        int cnt, col0;
+        T xw[C];
+        auto gather = [&]() {
+            un = has ? un : 0u;
+            cnt = has ? cnt : 0;
+            if constexpr (VAR & kVarPartialX) {
+#pragma unroll
+                for (int k = 0; k < C; ++k) xw[k] = T(0);   // rows load their own x
+            } else if constexpr (VAR & kVarUnionX) {
+                // merged predicate: only the pieces some row of the block uses
+                load_window_union<T, C>(xbuf, un ? (uint32_t)col0 * (uint32_t)sizeof(T) : kOOB,
+                                        un, xw);
+            } else {
+                load_window<T, C>(xbuf, un ? (uint32_t)col0 * (uint32_t)sizeof(T) : kOOB, xw);
+            }
+        };
+        int skv, skm = 0, skc = 0, skp;
         __syncthreads();
-        st.rm.commit(s_mask, st.qm);
-        st.rc.commit(s_col, st.qc);
-        st.rp.commit(s_bp, st.qp);
-        st.rv.commit(s_val, st.qv);
-        const int skv = st.qv.skew, skm = st.qm.skew, skc = st.qc.skew, skp = st.qp.skew;
-        __syncthreads();
+        if constexpr (PB) {
+            // the block's masks and anchor are in this thread's registers:
+            // the gather goes out before the tile is copied to LDS
+            st.union_count(un, cnt);
+            col0 = st.cw;
+            gather();
+            st.commit_block((uint8_t *)s_mask, (int *)s_col, has);
+            st.rp.commit(s_bp, st.qp);
+            st.rv.commit(s_val, st.qv);
+            skv = st.qv.skew;
+            skp = st.qp.skew;
+            __builtin_amdgcn_sched_barrier(0);
+            st.issue(q0, q1, c0, c1, w0, w1, val, masks, blk_col, blk_ptr);
+            __builtin_amdgcn_sched_barrier(0);
+            __syncthreads();
+        } else {
+            st.rm.commit(s_mask, st.qm);
+            st.rc.commit(s_col, st.qc);
+            st.rp.commit(s_bp, st.qp);
+            st.rv.commit(s_val, st.qv);
+            skv = st.qv.skew;
+            skm = st.qm.skew;
+            skc = st.qc.skew;
+            skp = st.qp.skew;
+            __syncthreads();
+            // the block's masks and anchor are read whether or not the thread
+            // has a block (index 0 then, inside the buffers; the results are
+            // dropped), so the reads go out together
+            lds_block_union_count<R, C>((const uint8_t *)s_mask + skm, tb, un, cnt);
+            col0 = ((const int *)((const uint8_t *)s_col + skc))[tb];
+            gather();
+            __builtin_amdgcn_sched_barrier(0);
+            st.issue(q0, q1, c0, c1, w0, w1, val, masks, blk_col, blk_ptr);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         const uint8_t *smb = (const uint8_t *)s_mask + skm;
         const int *scol = (const int *)((const uint8_t *)s_col + skc);
         const int *sbp = (const int *)((const uint8_t *)s_bp + skp);
         const T *sval = (const T *)((const uint8_t *)s_val + skv);
-        const int np = p1 - p0;
-        const int nbt = b1 - b0;
-
-        // 3. single x load per block (thread per block) ...  The block's
-        // masks and anchor are read whether or not the thread has a block
-        // (index 0 then, inside the buffers; the results are dropped), so the
-        // reads go out together instead of one behind the other.
-        const bool has = th < nbt;
-        const int tb = has ? th : 0;
-        unsigned un;
-        int cnt;
-        lds_block_union_count<R, C>(smb, tb, un, cnt);
-        un = has ? un : 0u;
-        cnt = has ? cnt : 0;
-        const int col0 = scol[tb];
-        // The whole window x[anchor .. anchor+C) in 16-byte loads: the buffer
-        // range check is per dword, so a window running past the last column
-        // reads zeros there, and blocks whose rows use no column read nothing.
-        T xw[C];
-        if constexpr (VAR & kVarPartialX) {
-#pragma unroll
-            for (int k = 0; k < C; ++k) xw[k] = T(0);   // rows load their own x
-        } else if constexpr (VAR & kVarUnionX) {
-            // merged predicate: only the pieces some row of the block uses
-            load_window_union<T, C>(xbuf, un ? (uint32_t)col0 * (uint32_t)sizeof(T) : kOOB, un,
-                                    xw);
-        } else {
-            load_window<T, C>(xbuf, un ? (uint32_t)col0 * (uint32_t)sizeof(T) : kOOB, xw);
-        }
-        // ... then the next tile's staging loads, so both are in flight
-        // together and waiting for the gathers does not wait for them (the
-        // scheduling barriers keep the compiler from reordering the groups).
-        // On the last tile the current tile is re-requested (cache hits):
-        // keeping the issue unconditional keeps the load counters exact on
-        // every path.
-        __builtin_amdgcn_sched_barrier(0);
-        st.issue(q0, q1, c0, c1, w0, w1, val, masks, blk_col, blk_ptr);
-        __builtin_amdgcn_sched_barrier(0);
 
         // 2. block value offsets (workgroup exclusive scan of block popcounts)
         const int incl = wave_incl_scan(cnt);
