@@ -278,7 +278,7 @@ __attribute__((amdgpu_waves_per_eu(stream_residency<T, R, C, NVG, VAR>()))) void
                 load_window<T, C>(xbuf, un ? (uint32_t)col0 * (uint32_t)sizeof(T) : kOOB, xw);
             }
         };
-        int skv, skm = 0, skc = 0, skp;
+        int skv, skm = 0, skc = 0, skp, incl;
         __syncthreads();
         if constexpr (PB) {
             // the block's masks and anchor are in this thread's registers:
@@ -294,6 +294,11 @@ __attribute__((amdgpu_waves_per_eu(stream_residency<T, R, C, NVG, VAR>()))) void
             __builtin_amdgcn_sched_barrier(0);
             st.issue(q0, q1, c0, c1, w0, w1, val, masks, blk_col, blk_ptr);
             __builtin_amdgcn_sched_barrier(0);
+            // 2. block value offsets: the wavefront scan of the block value
+            // counts runs from registers too, so the wavefront totals share
+            // the tile's barrier
+            incl = wave_incl_scan(cnt);
+            if (lane == kWave - 1) s_wsum[wv] = incl;
             __syncthreads();
         } else {
             st.rm.commit(s_mask, st.qm);
@@ -320,19 +325,28 @@ __attribute__((amdgpu_waves_per_eu(stream_residency<T, R, C, NVG, VAR>()))) void
         const int *sbp = (const int *)((const uint8_t *)s_bp + skp);
         const T *sval = (const T *)((const uint8_t *)s_val + skv);
 
-        // 2. block value offsets (workgroup exclusive scan of block popcounts)
-        const int incl = wave_incl_scan(cnt);
-        if (lane == kWave - 1) s_wsum[wv] = incl;
-        if (has) {
+        if constexpr (!PB) {
+            // 2. block value offsets (workgroup exclusive scan of block
+            // popcounts): the wavefront totals need a barrier of their own
+            incl = wave_incl_scan(cnt);
+            if (lane == kWave - 1) s_wsum[wv] = incl;
+            if (has) {
 #pragma unroll
-            for (int k = 0; k < C; ++k) s_x[k * BT + tb] = xw[k];
+                for (int k = 0; k < C; ++k) s_x[k * BT + tb] = xw[k];
+            }
+            __syncthreads();
         }
-        __syncthreads();
         {
             int before = 0;
 #pragma unroll
             for (int w2 = 0; w2 < kWG / kWave; ++w2) before += w2 < wv ? s_wsum[w2] : 0;
-            if (has) s_boff[tb] = before + incl - cnt;
+            if (has) {
+                s_boff[tb] = before + incl - cnt;
+                if constexpr (PB) {
+#pragma unroll
+                    for (int k = 0; k < C; ++k) s_x[k * BT + tb] = xw[k];
+                }
+            }
         }
         __syncthreads();
 
