@@ -337,6 +337,50 @@ struct BlockStage {
     }
 };
 
+// Value-mode (r = 1, byte masks) tile stage with the block metadata in
+// registers: thread t owns blocks 4t .. 4t+3 of the tile and loads their
+// four byte masks (two aligned dwords, shifted into place: the tile's first
+// block need not start a dword) and their four anchors (four dword loads) itself;
+// values and panel bounds are staged as 16-byte vectors, as in TileStage.
+template <typename T, int C, int NVG>
+struct VBlockStage {
+    using Cfg = StreamCfg<T, 1, C, NVG>;
+    static_assert(sizeof(typename MaskOf<C>::type) == 1 && Cfg::BPT == 4, "byte masks, 4 blocks");
+    Range16 qv, qp;
+    RegStage<Cfg::NV> rv;
+    RegStage<Cfg::NP> rp;
+    unsigned m0, m1;   // the dwords holding this thread's four masks
+    int sh;            // bytes from the first dword's start to the tile's first mask
+    unsigned cl[4];    // the four anchors
+
+    __device__ __forceinline__ void issue(int p0, int p1, int b0, int b1, int v0, int v1,
+                                          const T *val, const void *masks, const int32_t *blk_col,
+                                          const int32_t *blk_ptr) {
+        qv = range16(val, (int64_t)v0 * (int64_t)sizeof(T), (int64_t)v1 * (int64_t)sizeof(T));
+        qp = range16(blk_ptr, (int64_t)p0 * 4, (int64_t)(p1 + 1) * 4);
+        const int64_t ma = (int64_t)b0 & ~(int64_t)3;
+        sh = b0 & 3;
+        // whole dwords (the range check is per dword): the last one may hold
+        // masks of the next tile, which the caller drops
+        const Buf mb = make_buf((const uint8_t *)masks + ma, ((int64_t)b1 - ma + 3) & ~(int64_t)3);
+        const Buf cb = make_buf(blk_col + b0, (int64_t)(b1 - b0) * 4);
+        const uint32_t th = threadIdx.x;
+        TileStage<T, 1, C, NVG>::fixed(rv, qv);
+        TileStage<T, 1, C, NVG>::fixed(rp, qp);
+        m0 = __builtin_amdgcn_raw_buffer_load_b32(mb.r, (int)(th * 4u), 0, 0);
+        m1 = __builtin_amdgcn_raw_buffer_load_b32(mb.r, (int)(th * 4u + 4u), 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            cl[q] = __builtin_amdgcn_raw_buffer_load_b32(cb.r, (int)(th * 16u + 4u * q), 0, 0);
+    }
+
+    // mask of the thread's block q (0..3)
+    __device__ __forceinline__ unsigned mask(int q) const {
+        const uint64_t w = ((uint64_t)m1 << 32) | m0;
+        return (unsigned)(w >> (8 * (sh + q))) & 0xffu;
+    }
+};
+
 // Row sums of a value-mode tile.  Rows are contiguous value ranges
 // (range(row, vs, ve)).  Every row gets S sub-lanes (S the largest power of
 // two with np*S <= 256, at most 64) that stride its values and meet in a

@@ -408,8 +408,10 @@ __attribute__((amdgpu_waves_per_eu(vstream_residency<T, C, NVG>()))) void k_spmv
     constexpr int VCAP = Cfg::VVEC * 16 / (int)sizeof(T);    // value slots of a tile
     constexpr int NX = (VCAP + kWG - 1) / kWG;               // value slots per thread
     __shared__ v4u s_val[Cfg::VVEC];
-    __shared__ v4u s_mask[Cfg::MVEC];
-    __shared__ v4u s_col[Cfg::CVEC];
+    // block masks and anchors through LDS only for 16-bit masks
+    constexpr bool kLdsMeta = sizeof(MT) != 1;
+    __shared__ v4u s_mask[kLdsMeta ? Cfg::MVEC : 1];
+    __shared__ v4u s_col[kLdsMeta ? Cfg::CVEC : 1];
     __shared__ v4u s_bp[Cfg::PVEC];
     __shared__ int s_vcol[VCAP];
     // first value of every block inside the tile (< VCAP, so 16 bits do)
@@ -431,7 +433,10 @@ __attribute__((amdgpu_waves_per_eu(vstream_residency<T, C, NVG>()))) void k_spmv
     int p0 = tile_p[t_begin], p1 = f0 ? p0 + 1 : tile_p[t_begin + 1];
     int b0 = tile_b[t_begin], b1 = tile_b[t_begin + 1];
     int v0 = tile_v[t_begin], v1 = tile_v[t_begin + 1];
-    TileStage<T, 1, C, NVG> st;
+    // byte masks (c <= 8): each thread loads its own blocks' masks and anchors
+    constexpr bool PB = sizeof(MT) == 1;
+    using Stage = std::conditional_t<PB, VBlockStage<T, C, NVG>, TileStage<T, 1, C, NVG>>;
+    Stage st;
     st.issue(p0, p1, b0, b1, v0, v1, val, masks, blk_col, blk_ptr);
 
     for (int64_t t = t_begin; t < t_end; ++t) {
@@ -441,19 +446,6 @@ __attribute__((amdgpu_waves_per_eu(vstream_residency<T, C, NVG>()))) void k_spmv
         const int q0 = tile_p[tn], q1 = g0 ? q0 + 1 : tile_p[tn + 1];
         const int c0 = tile_b[tn], c1 = tile_b[tn + 1];
         const int w0 = tile_v[tn], w1 = tile_v[tn + 1];
-
-        __syncthreads();
-        st.rm.commit(s_mask, st.qm);
-        st.rc.commit(s_col, st.qc);
-        st.rp.commit(s_bp, st.qp);
-        st.rv.commit(s_val, st.qv);
-        if (th == 0) s_nlong = 0;
-        const int skv = st.qv.skew, skm = st.qm.skew, skc = st.qc.skew, skp = st.qp.skew;
-        __syncthreads();
-        const MT *smk = (const MT *)((const uint8_t *)s_mask + skm);
-        const int *scol = (const int *)((const uint8_t *)s_col + skc);
-        const int *sbp = (const int *)((const uint8_t *)s_bp + skp);
-        T *sval = (T *)((uint8_t *)s_val + skv);
         const int np = p1 - p0;
         const int nbt = b1 - b0;
         const int nv = v1 - v0;
@@ -462,17 +454,53 @@ __attribute__((amdgpu_waves_per_eu(vstream_residency<T, C, NVG>()))) void k_spmv
         // owns blocks BPT*th .. BPT*th+BPT-1
         constexpr int BPT = Cfg::BPT;
         unsigned m[BPT];
-        int cnt[BPT], own = 0;
+        int cnt[BPT], own = 0, incl, skv, skp;
+        const int *scol = nullptr;
+        if constexpr (PB) {
+            // masks in registers: the scan needs no LDS and runs before the
+            // tile's barrier
 #pragma unroll
-        for (int q = 0; q < BPT; ++q) {
-            const int tb = BPT * th + q;
-            m[q] = tb < nbt ? (unsigned)smk[tb] : 0u;
-            cnt[q] = __popc(m[q]);
-            own += cnt[q];
+            for (int q = 0; q < BPT; ++q) {
+                const int tb = BPT * th + q;
+                m[q] = tb < nbt ? st.mask(q) : 0u;
+                cnt[q] = __popc(m[q]);
+                own += cnt[q];
+            }
+            incl = wave_incl_scan(own);
+            __syncthreads();
+            st.rp.commit(s_bp, st.qp);
+            st.rv.commit(s_val, st.qv);
+            if (th == 0) s_nlong = 0;
+            if (lane == kWave - 1) s_wsum[wv] = incl;
+            skv = st.qv.skew;
+            skp = st.qp.skew;
+            __syncthreads();
+        } else {
+            __syncthreads();
+            st.rm.commit(s_mask, st.qm);
+            st.rc.commit(s_col, st.qc);
+            st.rp.commit(s_bp, st.qp);
+            st.rv.commit(s_val, st.qv);
+            if (th == 0) s_nlong = 0;
+            skv = st.qv.skew;
+            skp = st.qp.skew;
+            const int skm = st.qm.skew, skc = st.qc.skew;
+            __syncthreads();
+            const MT *smk = (const MT *)((const uint8_t *)s_mask + skm);
+            scol = (const int *)((const uint8_t *)s_col + skc);
+#pragma unroll
+            for (int q = 0; q < BPT; ++q) {
+                const int tb = BPT * th + q;
+                m[q] = tb < nbt ? (unsigned)smk[tb] : 0u;
+                cnt[q] = __popc(m[q]);
+                own += cnt[q];
+            }
+            incl = wave_incl_scan(own);
+            if (lane == kWave - 1) s_wsum[wv] = incl;
+            __syncthreads();
         }
-        const int incl = wave_incl_scan(own);
-        if (lane == kWave - 1) s_wsum[wv] = incl;
-        __syncthreads();
+        const int *sbp = (const int *)((const uint8_t *)s_bp + skp);
+        T *sval = (T *)((uint8_t *)s_val + skv);
         int before = 0, total = 0;
 #pragma unroll
         for (int w2 = 0; w2 < kWG / kWave; ++w2) {
@@ -487,7 +515,9 @@ __attribute__((amdgpu_waves_per_eu(vstream_residency<T, C, NVG>()))) void k_spmv
             const int tb = BPT * th + q;
             if (tb < nbt) {
                 s_boff[tb] = (uint16_t)boff;
-                const int c0b = scol[tb];
+                int c0b;
+                if constexpr (PB) c0b = (int)st.cl[q];
+                else c0b = scol[tb];
                 unsigned mm = m[q];
                 int v = boff;
                 while (mm) {
