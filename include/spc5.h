@@ -172,6 +172,17 @@ typedef enum {
  * SPC5_EUNSUPPORTED (staged or rows kernel with x above 2 GiB). */
 int spc5_set_schedule(spc5_matrix *A, int kernel, int panels_per_tile);
 
+/* Process-wide tuning overrides, read from the environment once, at the first
+ * product that needs them (for measurements; results do not change):
+ *   SPC5_TILES_PER_WG=n  staged kernels: n consecutive tiles per workgroup
+ *                        (default: 8 on matrices of at least 32768 tiles,
+ *                        fewer on smaller ones);
+ *   SPC5_ROWS_MODE=s|d   staged kernel, r > 1: the set-bit (s) or the
+ *                        branch-free (d) rows loop (default: set-bit when a
+ *                        block row averages fewer than c/2 nonzeros);
+ *   SPC5_XCD_REMAP=0     workgroups in launch order instead of runs of 32
+ *                        consecutive ones per XCD. */
+
 /* Kernel variants of the staged forward product that reproduce the paper's
  * ablations (Table "res:perf:comp"); 0 restores the default.  Flags:
  *  SPC5_VARIANT_PARTIAL_X   "partial x load" (Section 3.1): every row loads
