@@ -173,7 +173,8 @@ typedef enum {
 int spc5_set_schedule(spc5_matrix *A, int kernel, int panels_per_tile);
 
 /* Process-wide tuning overrides, read from the environment once, at the first
- * product that needs them (for measurements; results do not change):
+ * product that needs them (for measurements; only SPC5_ROWS_MODE can change
+ * the last bits of y, through another order of summation):
  *   SPC5_TILES_PER_WG=n  staged kernels: n consecutive tiles per workgroup
  *                        (default: 8 on matrices of at least 32768 tiles,
  *                        fewer on smaller ones);
