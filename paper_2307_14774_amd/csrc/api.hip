@@ -224,9 +224,10 @@ void free_matrix(spc5_matrix *A) {
     DeviceGuard g(A->device);
     free_matrix(A->tr);
     free_pool(A);
-    for (void *p : {(void *)A->tr_lidx, (void *)A->tr_gpos, (void *)A->tr_src,
-                    A->tr_arow, (void *)A->tr_cbase, (void *)A->tr_hoff, (void *)A->tr_hbits,
-                    (void *)A->tr_hrow, (void *)A->tr_rlo, (void *)A->tr_edge_rows})
+    for (void *p : {(void *)A->tr_lidx, (void *)A->tr_rslot, (void *)A->tr_rbase,
+                    (void *)A->tr_rstart, (void *)A->tr_src, A->tr_arow, (void *)A->tr_cbase,
+                    (void *)A->tr_hoff, (void *)A->tr_hbits, (void *)A->tr_hrow,
+                    (void *)A->tr_rlo, (void *)A->tr_edge_rows})
         if (p) (void)hipFree(p);
     if (A->blk_ptr) (void)hipFree(A->blk_ptr);
     if (A->blk_col) (void)hipFree(A->blk_col);

@@ -45,8 +45,14 @@ struct spc5_matrix {
     // packed order to A^T's (see transpose_plan.hip)
     spc5_matrix *tr = nullptr;
     uint16_t *tr_lidx = nullptr;   // [nnz] pass 1: chunk-local value to write
-    int32_t *tr_gpos = nullptr;    // [nnz] pass 1: staging slot written
     uint16_t *tr_src = nullptr;    // [nnz] pass 2: bucket-local slot read
+    // runs (the values of one chunk of A inside one bucket of A^T, in slot
+    // order): window slot where each starts, its position in pass 1's output
+    // minus that slot, each bucket's first run
+    uint16_t *tr_rslot = nullptr;  // [nruns]
+    int32_t *tr_rbase = nullptr;  // [nruns]
+    int32_t *tr_rstart = nullptr;  // [nbuckets+1]
+    int64_t tr_nruns = 0;
     void *tr_arow = nullptr;       // [nnz] A's row of every packed value (pass 1): uint16
                                    // offsets from tr_cbase[chunk], or int32 when it is NULL
     int32_t *tr_cbase = nullptr;   // [nbuckets] base row of every chunk of A

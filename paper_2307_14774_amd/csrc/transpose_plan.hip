@@ -26,10 +26,10 @@
 //     (one LDS window), A's values get staging slots grouped by bucket
 //     (inside a bucket: A's packed order), and two passes run, each through
 //     LDS: pass 1 loads a contiguous chunk of 16384 values of A, forms their
-//     products and writes them out in slot order (one contiguous run per
-//     bucket); pass 2 loads one bucket's slots, reads them in A^T's order
-//     through 16-bit local indices and sums each row's run with a workgroup
-//     segmented scan.  A row inside one bucket is stored there; a row cut by
+//     products and stores them contiguously in slot order (one run per
+//     bucket the chunk reaches); pass 2 assembles one bucket's slots from
+//     those runs, reads them in A^T's order through 16-bit local indices and
+//     sums each row's run with a workgroup segmented scan.  A row inside one bucket is stored there; a row cut by
 //     bucket edges leaves its bucket-edge partial sums, added in bucket
 //     order by a fixup.  Every global access is contiguous, there are no
 //     atomics, and the result is reproducible bit for bit.  (Chunks are
@@ -39,6 +39,7 @@
 #include "wave.h"
 
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 #include <rocprim/iterator/counting_iterator.hpp>
 
 #include <algorithm>
@@ -138,19 +139,46 @@ __global__ void k_chunk_lists(int64_t nnz, int64_t w, const int32_t *__restrict_
     if (j < nnz) lidx[j] = (uint16_t)(order[by_chunk[j]] - (j / w) * w);
 }
 
+// Runs: slot t starts one when it is its bucket's first slot or holds a
+// value of another chunk of A than slot t-1 (inside a bucket the slots
+// follow A's packed order, so a chunk's values there are consecutive).
+__global__ void k_run_flags(int64_t nnz, int64_t w, int64_t wc, const int32_t *__restrict__ order,
+                            int32_t *__restrict__ flag) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nnz) flag[t] = (t % w == 0 || order[t] / wc != order[t - 1] / wc) ? 1 : 0;
+}
+
+// Run k = rnum[t] starting at slot t: its window slot u0 = t % w and its
+// base, the position in pass 1's output (lpos: the output position of every
+// slot) minus u0, so that window slot u of the run reads base + u; for a
+// bucket's first slot also the bucket's first run.  Inside a bucket the
+// bases never decrease: the runs follow the chunks in order, and a chunk's
+// output ends no later than where the next one's starts.
+__global__ void k_run_tables(int64_t nnz, int64_t w, const int32_t *__restrict__ flag,
+                             const int32_t *__restrict__ rnum, const int32_t *__restrict__ lpos,
+                             uint16_t *__restrict__ rslot, int32_t *__restrict__ rbase,
+                             int32_t *__restrict__ rstart) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nnz || !flag[t]) return;
+    const int k = rnum[t];
+    const int u0 = (int)(t % w);
+    rslot[k] = (uint16_t)u0;
+    rbase[k] = lpos[t] - u0;
+    if (u0 == 0) rstart[t / w] = k;
+}
+
 // Pass 1: workgroup c loads values [c*W, c*W + m) of A into LDS, each
-// multiplied by ybar at its row, then writes stage[gpos[j]] = win[lidx[j]]
-// over its slot-ordered list.  The products are formed in pairs of
-// consecutive values (4-byte loads of two 16-bit row offsets); the stores
-// go one list position per lane, consecutive lanes on consecutive positions,
-// so that one store instruction covers whole runs of consecutive slots (a
-// bucket's run from one chunk is a few dozen bytes).  Rows come as 16-bit
-// offsets from the chunk's base row (R16) or as full indices.
+// multiplied by ybar at its row, then writes position j of its list,
+// out[c*W + j] = win[lidx[c*W + j]]: the chunk's products in slot order,
+// bucket after bucket, stored contiguously (pass 2 gathers each bucket's
+// runs).  The products are formed in pairs of consecutive values (4-byte
+// loads of two 16-bit row offsets).  Rows come as 16-bit offsets from the
+// chunk's base row (R16) or as full indices.
 template <typename T, bool R16>
 __global__ __launch_bounds__(kChunkThreads) void k_move_products(
-    int64_t n, const uint16_t *__restrict__ lidx, const int32_t *__restrict__ gpos,
-    const T *__restrict__ in, const void *__restrict__ arow, const int32_t *__restrict__ cbase,
-    const T *__restrict__ ybar, T *__restrict__ stage) {
+    int64_t n, const uint16_t *__restrict__ lidx, const T *__restrict__ in,
+    const void *__restrict__ arow, const int32_t *__restrict__ cbase, const T *__restrict__ ybar,
+    T *__restrict__ stage) {
     constexpr int W = kChunkValues;
     constexpr int P = W / (2 * kChunkThreads);     // value pairs per thread
     constexpr int Q = W / kChunkThreads;           // list positions per thread
@@ -159,14 +187,11 @@ __global__ __launch_bounds__(kChunkThreads) void k_move_products(
     const int64_t c0 = cb * W;
     const int m = (int)min((int64_t)W, n - c0);
     const int th = threadIdx.x;
-    // the list's slots and local indices: independent of the products, read
-    // first
-    int32_t g[Q];
+    // the list's local indices: independent of the products, read first
     uint32_t l[Q];
 #pragma unroll
     for (int e = 0; e < Q; ++e) {
         const int j = th + e * kChunkThreads;
-        g[e] = j < m ? gpos[c0 + j] : 0;
         l[e] = j < m ? (uint32_t)lidx[c0 + j] : 0u;
     }
     if constexpr (R16) {
@@ -192,7 +217,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_move_products(
 #pragma unroll
     for (int e = 0; e < Q; ++e) {
         const int j = th + e * kChunkThreads;
-        if (j < m) stage[(uint32_t)g[e]] = win[l[e]];
+        if (j < m) stage[c0 + j] = win[l[e]];
     }
 }
 
@@ -231,8 +256,9 @@ __device__ __forceinline__ SegSum<T> seg_join(SegSum<T> a, SegSum<T> b) {
     return {a.f | b.f, b.f ? b.v : a.v + b.v};
 }
 
-// Pass 2: workgroup b loads bucket b's slots [b*W, b*W + m) into LDS.
-// Thread t owns positions t*16 .. t*16+15 of the bucket in A^T's CSR order;
+// Pass 2: workgroup b assembles bucket b's slots [b*W, b*W + m) in LDS from
+// the runs of pass 1's output (a run: the values of one chunk of A inside
+// the bucket, consecutive both there and in the chunk's output).  Thread t owns positions t*16 .. t*16+15 of the bucket in A^T's CSR order;
 // position q's product is win[src[q]].  The heads (first positions of the
 // nonempty rows of A^T) come from a bitmap over all positions, read straight
 // from memory; a workgroup segmented scan carries each row's running sum,
@@ -245,23 +271,23 @@ __device__ __forceinline__ SegSum<T> seg_join(SegSum<T> a, SegSum<T> b) {
 // to the rows it owns, [rlo[b], rlo[b+1]): those whose first position lies
 // in the bucket (for the last bucket also the empty rows at the end), so
 // empty rows need no fill of their own; a wait for those stores before the
-// first barrier puts them ahead of the sums.
-// FP32: two workgroups per compute unit (64 KiB of LDS each) need 8 waves
+// barrier that completes the window puts them ahead of the sums.
+// FP32: four workgroups per compute unit (32 KiB of LDS each) need 8 waves
 // per SIMD, i.e. at most 64 VGPRs.
 template <typename T>
 __global__ __launch_bounds__(kBucketThreads)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
     int64_t n, const uint16_t *__restrict__ src, const T *__restrict__ stage,
-    const uint32_t *__restrict__ hbits, const int32_t *__restrict__ hoff,
+    const int32_t *__restrict__ rstart, const uint16_t *__restrict__ rslot,
+    const int32_t *__restrict__ rbase, const uint32_t *__restrict__ hbits,
+    const int32_t *__restrict__ hoff,
     const int32_t *__restrict__ hrow, const int32_t *__restrict__ rlo, T *__restrict__ head,
     T *__restrict__ tail, T *__restrict__ xbar) {
     constexpr int W = kBucketValues;
     constexpr int NWV = kBucketThreads / kWave;
-    constexpr int VPL = 16 / (int)sizeof(T);            // values per 16-byte load
-    constexpr int NLD = kSumPer / VPL;                   // loads per thread
     constexpr int kHr = 2;                               // head rows per thread read up front
     __shared__ T win[W];
-    __shared__ int s_f[NWV], s_c[NWV];
+    __shared__ int s_f[NWV], s_c[NWV], s_m[W / kBucketThreads * NWV];
     __shared__ T s_v[NWV];
     const int b = blockIdx.x;
     const int64_t q0 = (int64_t)b * W;
@@ -280,17 +306,61 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
         const int rl0 = rlo[b], rl1 = rlo[b + 1];
         for (int j = rl0 + th; j < rl1; j += kBucketThreads) xbar[j] = T(0);
     }
-    // the global reads of the products, issued together: the bucket's slots
-    // (16 consecutive values per thread; the staging array is padded past
-    // its end), this thread's 16 slot indices and its 17 head bits (bit 16:
-    // the next thread's first position, or the next bucket's)
-    typedef unsigned v4 __attribute__((ext_vector_type(4)));
-    v4 r[NLD];
-    {
-        const v4 *sp = (const v4 *)(stage + q0 + t0);
+    // The bucket's runs [rstart[b], rstart[b+1]) in slot order: run k starts
+    // at window slot rslot[k], and slot u of it holds pass 1's output at
+    // rbase[k] + u (the bases do not decrease along the bucket).  The slots
+    // are taken in 16 rows of 512, slot u = row * 512 + thread.
+    // 1. Each run's first slot is marked with its base plus one (the marks
+    // sit in the window's memory, in the first 4 bytes of their slots, until
+    // the products replace them).
+    constexpr int NR = W / kBucketThreads;               // rows of slots
+    constexpr int MS = (int)sizeof(T) / 4;               // ints per slot
+    const int r0 = rstart[b], r1 = rstart[b + 1];
+    int *wm = (int *)win;
 #pragma unroll
-        for (int g = 0; g < NLD; ++g) r[g] = t0 < m ? sp[g] : v4{0u, 0u, 0u, 0u};
+    for (int k = 0; k < NR; ++k) wm[(th + k * kBucketThreads) * MS] = 0;
+    __syncthreads();
+    for (int k = r0 + th; k < r1; k += kBucketThreads) wm[(int)rslot[k] * MS] = rbase[k] + 1;
+    __syncthreads();
+    // 2. The base of every slot is the largest mark at or before it: a
+    // wavefront maximum scan per row (kept in the slot), then one over the
+    // 128 row segments' maxima (every wavefront scans them itself).
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        int *ws = wm + (th + k * kBucketThreads) * MS;
+        const int a = wave_incl_max(*ws);
+        *ws = a;
+        if (lane == kWave - 1) s_m[k * NWV + wv] = a;
     }
+    __syncthreads();
+    static_assert(NR * NWV == 2 * kWave, "two row segments per lane");
+    const int sa = s_m[2 * lane], sb = s_m[2 * lane + 1];
+    int ep = __shfl_up(wave_incl_max(max(sa, sb)), 1);
+    ep = lane ? ep : 0;
+    // largest mark before segment s = k * NWV + wv: on lane s / 2
+    const int pre = (wv & 1) ? max(ep, sa) : ep;
+    // 3. The products from their runs, consecutive lanes on consecutive
+    // slots; a slot's scan value is read, and the slot then overwritten, by
+    // the thread that wrote it.  Slots past the bucket's end (last bucket)
+    // read the last product instead: never used, no branch.
+    const uint32_t lim = (uint32_t)min((int64_t)UINT32_MAX, n - 1);
+#pragma unroll
+    for (int h = 0; h < NR; h += 8) {
+        T v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = h + i;
+            const int before = __builtin_amdgcn_readlane(pre, (k * NWV + wv) >> 1);
+            const int u = th + k * kBucketThreads;
+            const int base = max(before, wm[u * MS]);
+            v[i] = stage[min((uint32_t)(base - 1) + (uint32_t)u, lim)];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) win[th + (h + i) * kBucketThreads] = v[i];
+    }
+    // this thread's 16 slot indices and its 17 head bits (bit 16: the next
+    // thread's first position, or the next bucket's)
+    typedef unsigned v4 __attribute__((ext_vector_type(4)));
     v4 w0 = {0u, 0u, 0u, 0u}, w1 = {0u, 0u, 0u, 0u};
     if (t0 < m) {
         const v4 *sp = (const v4 *)(src + q0 + t0);
@@ -300,11 +370,6 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
     const int64_t pw = (q0 + t0) >> 5;                   // t0 & 31 is 0 or 16
     const uint32_t bw0 = hbits[pw];
     const uint32_t bw1 = (t0 & 31) ? hbits[pw + 1] : 0u;
-    {
-        v4 *wp = (v4 *)(win + t0);
-#pragma unroll
-        for (int g = 0; g < NLD; ++g) wp[g] = r[g];
-    }
     // the zero stores complete before the barrier, so that the sums other
     // waves store to the same rows after it land later
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -438,12 +503,13 @@ static hipError_t launch_theta_transpose(const spc5_matrix *A, const T *vals, co
     T *head = edges, *tail = edges + nbk;
     if (A->tr_cbase)
         hipLaunchKernelGGL((k_move_products<T, true>), dim3(nch), dim3(kChunkThreads), 0, s, n,
-                           A->tr_lidx, A->tr_gpos, vals, A->tr_arow, A->tr_cbase, ybar, stage);
+                           A->tr_lidx, vals, A->tr_arow, A->tr_cbase, ybar, stage);
     else
         hipLaunchKernelGGL((k_move_products<T, false>), dim3(nch), dim3(kChunkThreads), 0, s, n,
-                           A->tr_lidx, A->tr_gpos, vals, A->tr_arow, A->tr_cbase, ybar, stage);
+                           A->tr_lidx, vals, A->tr_arow, A->tr_cbase, ybar, stage);
     hipLaunchKernelGGL(k_bucket_sums<T>, dim3(nbk), dim3(kBucketThreads), 0, s, n, A->tr_src,
-                       (const T *)stage, A->tr_hbits, A->tr_hoff, A->tr_hrow, A->tr_rlo, head,
+                       (const T *)stage, A->tr_rstart, A->tr_rslot, A->tr_rbase, A->tr_hbits,
+                       A->tr_hoff, A->tr_hrow, A->tr_rlo, head,
                        tail, xbar);
     if (A->tr_nedge > 0) {
         const int64_t thr = A->tr_nedge * kWave;
@@ -468,7 +534,9 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
     int32_t *cbase = nullptr;
     void *arow = nullptr;
     int32_t *edge_rows = nullptr;
-    uint16_t *lidx = nullptr, *src = nullptr;
+    uint16_t *lidx = nullptr, *src = nullptr, *rslot = nullptr;
+    int32_t *rbase = nullptr, *rstart = nullptr;
+    int64_t nruns = 0;
     size_t tmp_bytes = 0;
     auto cleanup = [&]() {
         for (void *p : {(void *)row_of, (void *)col_of, (void *)key_s, (void *)idx_s,
@@ -480,7 +548,7 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
         free_matrix(T);
         for (void *p : {(void *)perm, (void *)lidx, (void *)src, arow, (void *)hoff,
                         (void *)hbits, (void *)hrow, (void *)rlo, (void *)edge_rows,
-                        (void *)cbase})
+                        (void *)cbase, (void *)rslot, (void *)rbase, (void *)rstart})
             if (p) (void)hipFree(p);
         return st;
     };
@@ -671,15 +739,54 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
         if ((e = sort(row_of, idx_s, perm)) != hipSuccess)
             return fail_all(hip_fail(e, "sorting by chunk"));
         hipLaunchKernelGGL(k_chunk_lists, dim3(grid), dim3(256), 0, s, nnz, WC, key_s, perm, lidx);
+        // runs for pass 2: flags (row_of), their numbers (idx_s), the output
+        // position of every slot (col_of: the inverse of the lists)
+        hipLaunchKernelGGL(k_run_flags, dim3(grid), dim3(256), 0, s, nnz, W, WC, key_s, row_of);
+        hipLaunchKernelGGL(k_invert, dim3(grid), dim3(256), 0, s, nnz, perm, col_of);
+        size_t need = 0;
+        if ((e = rocprim::exclusive_scan(nullptr, need, row_of, idx_s, 0, (size_t)nnz,
+                                         rocprim::plus<int32_t>(), s)) != hipSuccess)
+            return fail_all(hip_fail(e, "numbering the runs"));
+        if (need > tmp_bytes) {
+            if (tmp) (void)hipFree(tmp);
+            tmp = nullptr;
+            if ((e = hipMalloc(&tmp, need)) != hipSuccess)
+                return fail_all(hip_fail(e, "numbering the runs"));
+            tmp_bytes = need;
+        }
+        if ((e = rocprim::exclusive_scan(tmp, need, row_of, idx_s, 0, (size_t)nnz,
+                                         rocprim::plus<int32_t>(), s)) != hipSuccess)
+            return fail_all(hip_fail(e, "numbering the runs"));
+        int32_t tl[2] = {0, 0};
+        if ((e = hipMemcpyAsync(&tl[0], idx_s + nnz - 1, 4, hipMemcpyDeviceToHost, s)) !=
+                hipSuccess ||
+            (e = hipMemcpyAsync(&tl[1], row_of + nnz - 1, 4, hipMemcpyDeviceToHost, s)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return fail_all(hip_fail(e, "counting the runs"));
+        nruns = (int64_t)tl[0] + tl[1];
+        const int32_t nr32 = (int32_t)nruns;
+        if ((e = hipMalloc((void **)&rslot, (size_t)nruns * 2 + kPad)) != hipSuccess ||
+            (e = hipMalloc((void **)&rbase, (size_t)nruns * 4 + kPad)) != hipSuccess ||
+            (e = hipMalloc((void **)&rstart, (size_t)(nbk + 1) * 4 + kPad)) != hipSuccess ||
+            (e = hipMemcpy(rstart + nbk, &nr32, 4, hipMemcpyHostToDevice)) != hipSuccess)
+            return fail_all(hip_fail(e, "allocating the runs"));
+        hipLaunchKernelGGL(k_run_tables, dim3(grid), dim3(256), 0, s, nnz, W, row_of, idx_s,
+                           col_of, rslot, rbase, rstart);
         if ((e = hipGetLastError()) != hipSuccess)
             return fail_all(hip_fail(e, "building the value move"));
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess)
         return fail_all(hip_fail(e, "building the transpose plan"));
     cleanup();
+    // the lists' slots served only to find the runs
+    if (perm) (void)hipFree(perm);
     A->tr = T;
     A->tr_lidx = lidx;
-    A->tr_gpos = perm;
+    A->tr_rslot = rslot;
+    A->tr_rbase = rbase;
+    A->tr_rstart = rstart;
+    A->tr_nruns = nruns;
     A->tr_src = src;
     A->tr_arow = arow;
     A->tr_cbase = cbase;
