@@ -250,10 +250,10 @@ int spc5_spmv_values(const spc5_matrix *A, const void *values, const void *x,
  * over the stored A^T.  Caller values: each product value * ybar[row] is
  * formed in A's packed order and the products are summed in A^T's CSR order,
  * in two passes through the calling stream's scratch (nnz values plus two
- * per 8192 nonzeros): a scatter of the products into staging slots grouped
- * by position in A^T, then per group a gather in A^T's order and segmented
- * row sums (rows cut by a group edge are completed by a small fixup in
- * group order). */
+ * per 8192 nonzeros): each chunk of A stores its products contiguously,
+ * grouped by position in A^T; then each group gathers its runs from the
+ * chunks, reads them in A^T's order and forms segmented row sums (rows cut
+ * by a group edge are completed by a small fixup in group order). */
 int spc5_spmv_transpose(const spc5_matrix *A, const void *ybar, void *xbar,
                         void *stream);
 int spc5_spmv_transpose_values(const spc5_matrix *A, const void *values,

@@ -29,12 +29,14 @@
 //     products and stores them contiguously in slot order (one run per
 //     bucket the chunk reaches); pass 2 assembles one bucket's slots from
 //     those runs, reads them in A^T's order through 16-bit local indices and
-//     sums each row's run with a workgroup segmented scan.  A row inside one bucket is stored there; a row cut by
-//     bucket edges leaves its bucket-edge partial sums, added in bucket
-//     order by a fixup.  Every global access is contiguous, there are no
-//     atomics, and the result is reproducible bit for bit.  (Chunks are
-//     larger than buckets: longer runs per bucket in pass 1; smaller
-//     windows, so more workgroups resident per compute unit, in pass 2.)
+//     sums each row's run with a workgroup segmented scan.  A row inside one
+//     bucket is stored there; a row cut by bucket edges leaves its
+//     bucket-edge partial sums, added in bucket order by a fixup.  Apart
+//     from the runs (a few dozen bytes each on a power-law graph, shared in
+//     L2 by neighbouring buckets) every global access is contiguous; there
+//     are no atomics, and the result is reproducible bit for bit.  (Chunks
+//     are larger than buckets: longer runs; smaller windows, so more
+//     workgroups resident per compute unit, in pass 2.)
 #include "spc5_internal.h"
 #include "wave.h"
 
@@ -137,6 +139,20 @@ __global__ void k_chunk_lists(int64_t nnz, int64_t w, const int32_t *__restrict_
                               const int32_t *__restrict__ by_chunk, uint16_t *__restrict__ lidx) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j < nnz) lidx[j] = (uint16_t)(order[by_chunk[j]] - (j / w) * w);
+}
+
+// Inclusive maximum scan over the wavefront, the DPP steps of
+// wave_incl_scan; lanes that a step shifts in from outside their row read 0,
+// so the values must be non-negative.  Every lane must be active.
+__device__ __forceinline__ int wave_incl_max(int v) {
+    constexpr int kRowShr = 0x110, kBcast15 = 0x142, kBcast31 = 0x143;
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kRowShr + 1, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kRowShr + 2, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kRowShr + 4, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kRowShr + 8, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kBcast15, 0xa, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, kBcast31, 0xc, 0xf, false));
+    return v;
 }
 
 // Runs: slot t starts one when it is its bucket's first slot or holds a

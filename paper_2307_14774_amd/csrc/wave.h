@@ -32,20 +32,6 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
-// Inclusive maximum scan over the wavefront, the same DPP steps as
-// wave_incl_scan; lanes that a step shifts in from outside their row read 0,
-// so the values must be non-negative.  Every lane must be active.
-__device__ __forceinline__ int wave_incl_max(int v) {
-    constexpr int kRowShr = 0x110, kBcast15 = 0x142, kBcast31 = 0x143;
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, kRowShr + 1, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, kRowShr + 2, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, kRowShr + 4, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, kRowShr + 8, 0xf, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, kBcast15, 0xa, 0xf, false));
-    v = max(v, __builtin_amdgcn_update_dpp(0, v, kBcast31, 0xc, 0xf, false));
-    return v;
-}
-
 // Workgroups are dispatched round-robin over the XCDs (workgroup w goes to
 // XCD w % 8).  Remap the workgroup index so that each XCD walks one contiguous
 // range of tiles: neighbouring tiles share x segments, which then stay in
