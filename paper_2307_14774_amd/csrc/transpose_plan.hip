@@ -301,7 +301,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
     T *__restrict__ tail, T *__restrict__ xbar) {
     constexpr int W = kBucketValues;
     constexpr int NWV = kBucketThreads / kWave;
-    constexpr int kHr = 2;                               // head rows per thread read up front
+    constexpr int kHr = sizeof(T) == 4 ? 1 : 2;          // head rows per thread read up front
     __shared__ T win[W];
     __shared__ int s_f[NWV], s_c[NWV], s_m[W / kBucketThreads * NWV];
     __shared__ T s_v[NWV];
@@ -322,6 +322,18 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
         const int rl0 = rlo[b], rl1 = rlo[b + 1];
         for (int j = rl0 + th; j < rl1; j += kBucketThreads) xbar[j] = T(0);
     }
+    // this thread's 16 slot indices and its 17 head bits (bit 16: the next
+    // thread's first position, or the next bucket's), read up front
+    typedef unsigned v4 __attribute__((ext_vector_type(4)));
+    v4 w0 = {0u, 0u, 0u, 0u}, w1 = {0u, 0u, 0u, 0u};
+    if (t0 < m) {
+        const v4 *sp = (const v4 *)(src + q0 + t0);
+        w0 = sp[0];
+        w1 = sp[1];
+    }
+    const int64_t pw = (q0 + t0) >> 5;                   // t0 & 31 is 0 or 16
+    const uint32_t bw0 = hbits[pw];
+    const uint32_t bw1 = (t0 & 31) ? hbits[pw + 1] : 0u;
     // The bucket's runs [rstart[b], rstart[b+1]) in slot order: run k starts
     // at window slot rslot[k], and slot u of it holds pass 1's output at
     // rbase[k] + u (the bases do not decrease along the bucket).  The slots
@@ -374,18 +386,6 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
 #pragma unroll
         for (int i = 0; i < 8; ++i) win[th + (h + i) * kBucketThreads] = v[i];
     }
-    // this thread's 16 slot indices and its 17 head bits (bit 16: the next
-    // thread's first position, or the next bucket's)
-    typedef unsigned v4 __attribute__((ext_vector_type(4)));
-    v4 w0 = {0u, 0u, 0u, 0u}, w1 = {0u, 0u, 0u, 0u};
-    if (t0 < m) {
-        const v4 *sp = (const v4 *)(src + q0 + t0);
-        w0 = sp[0];
-        w1 = sp[1];
-    }
-    const int64_t pw = (q0 + t0) >> 5;                   // t0 & 31 is 0 or 16
-    const uint32_t bw0 = hbits[pw];
-    const uint32_t bw1 = (t0 & 31) ? hbits[pw + 1] : 0u;
     // the zero stores complete before the barrier, so that the sums other
     // waves store to the same rows after it land later
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
