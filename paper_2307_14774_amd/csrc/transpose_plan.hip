@@ -361,12 +361,13 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
         if (lane == kWave - 1) s_m[k * NWV + wv] = a;
     }
     __syncthreads();
-    static_assert(NR * NWV == 2 * kWave, "two row segments per lane");
-    const int sa = s_m[2 * lane], sb = s_m[2 * lane + 1];
+    constexpr int SPL = NR * NWV / kWave;                // row segments per lane
+    static_assert(SPL == 1 || SPL == 2, "one or two row segments per lane");
+    const int sa = s_m[SPL * lane], sb = SPL == 2 ? s_m[SPL * lane + 1] : 0;
     int ep = __shfl_up(wave_incl_max(max(sa, sb)), 1);
     ep = lane ? ep : 0;
-    // largest mark before segment s = k * NWV + wv: on lane s / 2
-    const int pre = (wv & 1) ? max(ep, sa) : ep;
+    // largest mark before segment s = k * NWV + wv: on lane s / SPL
+    const int pre = (SPL == 2 && (wv & 1)) ? max(ep, sa) : ep;
     // 3. The products from their runs, consecutive lanes on consecutive
     // slots; a slot's scan value is read, and the slot then overwritten, by
     // the thread that wrote it.  Slots past the bucket's end (last bucket)
@@ -378,7 +379,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int k = h + i;
-            const int before = __builtin_amdgcn_readlane(pre, (k * NWV + wv) >> 1);
+            const int before = __builtin_amdgcn_readlane(pre, (k * NWV + wv) / SPL);
             const int u = th + k * kBucketThreads;
             const int base = max(before, wm[u * MS]);
             v[i] = stage[min((uint32_t)(base - 1) + (uint32_t)u, lim)];
