@@ -179,3 +179,31 @@ def test_full_size_batch_256(dtype, dev):
     B.free()
     for M in Ms:
         M.free()
+
+
+@pytest.mark.parametrize("dtype", ["float32", "float64"])
+def test_full_size_graph_theta_transpose(dtype, dev):
+    """The caller-values transpose on the 2^20-row Zipf graph at full size
+    (16.8 M nonzeros: 1024 chunks of A, about a thousand runs per bucket of
+    A^T, the popular columns' rows of A^T across many buckets), with small
+    integer theta and ybar: every partial sum stays below 2^24, so FP32 is
+    exact too; compared bit for bit with the oracle, twice in a row into an
+    x_bar first filled with NaN."""
+    from paper_2307_14774_amd import spc5 as S
+    say(f"full Zipf graph theta transpose {dtype}")
+    G = W.zipf_graph(1 << 20, seed=0)
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    M = S.Spc5Matrix.from_csr(G.rowptr, G.colidx, G.values, G.ncols, 1, 8, dtype)
+    M.prepare_transpose(1, 8)
+    rng = np.random.default_rng(81)
+    for rep in range(2):
+        # beta(1,8): the packed order is the CSR order
+        theta = rng.integers(-3, 4, M.info.nnz).astype(np.float64)
+        wv = rng.integers(-4, 5, G.nrows).astype(np.float64)
+        xb = torch.full((G.ncols,), float("nan"), dtype=tdt, device=dev)
+        M.transpose(torch.from_numpy(wv).to(dev, tdt), xb,
+                    values=torch.from_numpy(theta).to(dev, tdt))
+        got = xb.cpu().double().numpy()
+        ref = oracle.csr_spmv_t(G.rowptr, G.colidx, theta, wv, G.ncols)
+        assert np.array_equal(got, ref), (rep, int(np.sum(got != ref)))
+    M.free()

@@ -684,6 +684,43 @@ def test_transpose_values_window_edges(dtype, rc, dev):
     M.free()
 
 
+def shifted_diagonal_matrix(n):
+    """Rows 0 .. n-4097 hold one entry each, at column i+1; the last 4096 rows
+    hold one entry each in column 0.  A^T's CSR order then lists the last
+    4096 packed values first and every other value 4096 positions after its
+    packed index, so a bucket of 8192 positions straddles each chunk edge of
+    16384 values: a run that ends its chunk meets a run that starts the next
+    chunk inside one bucket (equal bases).  Small integer values."""
+    rng = np.random.default_rng(n)
+    rows = np.arange(n, dtype=np.int64)
+    cols = np.where(rows < n - 4096, rows + 1, 0).astype(np.int32)
+    rowptr = np.arange(n + 1, dtype=np.int64)
+    values = rng.integers(-3, 4, n).astype(np.float64)
+    return rowptr, cols, values, n - 4096 + 1
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("n", [20_000, 70_001])
+def test_transpose_values_chunk_edge_runs(dtype, n, dev):
+    """Caller values theta through the two-pass move where runs of two chunks
+    meet inside a bucket (shifted_diagonal_matrix): bit for bit against the
+    oracle, x_bar first filled with NaN."""
+    S = spc5()
+    rowptr, colidx, values, ncols = shifted_diagonal_matrix(n)
+    say(f"transpose chunk-edge runs {dtype} n={n}")
+    M = S.Spc5Matrix.from_csr(rowptr, colidx, values, ncols, 1, 8, dtype)
+    M.prepare_transpose(1, 8)
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    rng = np.random.default_rng(91)
+    wv = rng.integers(-4, 5, n).astype(np.float64)
+    theta = rng.integers(-3, 4, n).astype(np.float64)    # beta(1,8): packed order = CSR order
+    xb = torch.full((ncols,), float("nan"), dtype=tdt, device=dev)
+    M.transpose(to_dev(wv, dev, tdt), xb, values=to_dev(theta, dev, tdt))
+    got = xb.cpu().double().numpy()
+    assert np.array_equal(got, oracle.csr_spmv_t(rowptr, colidx, theta, wv, ncols))
+    M.free()
+
+
 @pytest.mark.parametrize("plan", [False, True], ids=["scatter", "plan"])
 @pytest.mark.parametrize("rc", MAIN + [(8, 8), (3, 5)], ids=lambda t: "b%d_%d" % t)
 def test_transpose_unit_rows_and_integers(rc, plan, dev):
