@@ -751,7 +751,8 @@ int build_transpose_plan(spc5_matrix *A, int r, int c) {
         hipLaunchKernelGGL(k_invert, dim3(grid), dim3(256), 0, s, nnz, key_s, col_of);
         hipLaunchKernelGGL(k_bucket_src, dim3(grid), dim3(256), 0, s, nnz, W, col_of, idx_s, src);
         // pass 1 lists: slots sorted by chunk (stable, so ascending inside a
-        // chunk); gpos (perm's memory) = the slots, lidx = local value index
+        // chunk); perm = the slot of every list position (kept only until the
+        // runs are found), lidx = local value index
         hipLaunchKernelGGL(k_chunk_keys, dim3(grid), dim3(256), 0, s, nnz, WC, key_s, row_of);
         if ((e = sort(row_of, idx_s, perm)) != hipSuccess)
             return fail_all(hip_fail(e, "sorting by chunk"));
