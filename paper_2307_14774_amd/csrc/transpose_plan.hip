@@ -305,7 +305,10 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4))) void k_bucket_sums(
     __shared__ T win[W];
     __shared__ int s_f[NWV], s_c[NWV], s_m[W / kBucketThreads * NWV];
     __shared__ T s_v[NWV];
-    const int b = blockIdx.x;
+    // runs of 16 consecutive buckets per XCD: neighbouring buckets read
+    // adjacent runs of every chunk, so their cache lines are fetched into
+    // one L2 once
+    const int b = (int)xcd_chunks(blockIdx.x, gridDim.x, 16);
     const int64_t q0 = (int64_t)b * W;
     const int m = (int)min((int64_t)W, n - q0);
     const int th = threadIdx.x, lane = lane_id(), wv = th / kWave;
